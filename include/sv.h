@@ -1,0 +1,202 @@
+/*
+ * sv.h -- C-ABI of the MI355X (gfx950) state-vector simulator library libsv.so.
+ *
+ * The library applies quantum gates to a register of n qubits held as 2^n
+ * complex amplitudes in GPU memory, and reduces that vector to measurement
+ * probabilities and Z-string expectations.  It follows the problem statement
+ * of "Simulating Quantum Computers Using OpenCL" (arXiv 1805.00988):
+ *
+ *   - a register of n qubits is a vector of 2^n complex amplitudes that starts
+ *     in |0...0> (Sec. 2.1);
+ *   - a gate is a 2x2 complex matrix [[A, B], [C, D]] applied to target qubit
+ *     t, optionally controlled (Sec. 2.2, Sec. 2.3 and Alg. 1);
+ *   - measurement needs the probability |psi_x|^2 of every outcome x (Sec. 2.4).
+ *
+ * Conventions used by every entry point:
+ *   - qubit q is bit q of the amplitude index (qubit 0 least significant);
+ *   - amplitudes are interleaved (re, im): float2 for SV_C64, double2 for
+ *     SV_C128, amplitude x at byte offset x * sizeof(element);
+ *   - a matrix U of a k-qubit gate is 2^k x 2^k, row-major, complex entries
+ *     interleaved as (re, im) doubles, in HOST memory; bit j of its row/column
+ *     index is the value of qubit targets[j];
+ *   - a control mask selects the subspace where every masked bit is 1; the
+ *     gate acts as the identity elsewhere (Sec. 2.3, controlled variant).
+ *
+ * Ownership: every host array argument belongs to the caller and is read
+ * before the call returns.  Device buffers passed in (dev_buf, dev_out) belong
+ * to the caller; the library frees only memory it allocated itself.
+ *
+ * Ordering: a handle is bound to one HIP stream.  Calls enqueue their kernels
+ * on that stream and return without waiting, except calls that write a host
+ * result (host_* arguments), which wait for it.  A handle must not be used by
+ * two threads at once.
+ *
+ * Errors: every call validates its arguments on the host before enqueueing
+ * anything.  On failure it returns a negative sv_status, leaves the state
+ * unchanged and records a message readable with sv_last_error() (per thread).
+ * Asynchronous device faults surface as SV_EDEVICE from the next call that
+ * synchronises.  Unitarity of U is not checked; no call renormalises.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sv_state *sv_handle;
+
+enum sv_dtype { SV_C64 = 1, SV_C128 = 2 };
+
+enum sv_status {
+    SV_OK = 0,
+    SV_EINVAL = -1,       /* bad argument (qubit out of range, duplicate, NULL, ...) */
+    SV_ENOMEM = -2,       /* the state (or a work buffer) does not fit in device memory */
+    SV_EDEVICE = -3,      /* a HIP runtime call failed */
+    SV_EUNSUPPORTED = -4  /* valid request the library does not implement */
+};
+
+/* Arithmetic of sv_apply_fused blocks. */
+enum sv_prec {
+    SV_PREC_NATIVE = 0,     /* the state's own precision on the vector ALUs */
+    SV_PREC_FP32 = 1,       /* FP32 matrix-core (MFMA) products, FP32 accumulate */
+    SV_PREC_SPLIT_BF16 = 2  /* each FP32 operand split into bf16 hi + lo; three
+                               bf16 MFMA products (hi*hi, hi*lo, lo*hi) with FP32
+                               accumulate */
+};
+
+/* Named gates of an sv_op (see sv_op.kind). */
+enum sv_gate_kind {
+    SV_GATE_H = 1, SV_GATE_X = 2, SV_GATE_Y = 3, SV_GATE_Z = 4, SV_GATE_S = 5,
+    SV_GATE_T = 6,
+    SV_GATE_RX = 7, SV_GATE_RY = 8, SV_GATE_RZ = 9, /* exp(-i theta P / 2) */
+    SV_GATE_U1 = 10,                                 /* diag(1, e^{i theta}) */
+    SV_GATE_MATRIX = 11                              /* explicit 2x2 or 4x4 */
+};
+
+/* One gate of a circuit.  H..T follow the gate table of Sec. 1.3.2 (CNOT =
+ * SV_GATE_X with one control); U1 is the phase gate of the QFT benchmark
+ * (App. A).  n_targets is 1, or 2 for SV_GATE_MATRIX; matrix holds the
+ * 2^k x 2^k entries for SV_GATE_MATRIX only.  param_index >= 0 replaces theta
+ * by params[param_index] (parametrised gates RX RY RZ U1). */
+typedef struct sv_op {
+    int32_t kind;
+    int32_t n_targets;
+    int32_t targets[2];
+    uint64_t ctrl_mask;
+    int32_t param_index;
+    int32_t reserved;
+    double theta;
+    double matrix[32];
+} sv_op;
+
+/* Bytes of an n-qubit state: 2^n * 8 (SV_C64, the paper's 64 bits per
+ * amplitude, Sec. 2.1) or 2^n * 16 (SV_C128).  0 for invalid arguments. */
+size_t sv_state_bytes(int n_qubits, int dtype);
+
+/* Create a register of n_qubits (1..40) in |0...0> (Sec. 2.1).
+ * dev_buf: NULL to let the library allocate the 2^n amplitudes, else a device
+ * buffer of at least sv_state_bytes() bytes, 16-byte aligned, that the
+ * caller keeps alive until sv_free (e.g. a torch tensor).  hip_stream: the
+ * hipStream_t all work of this handle is ordered on (NULL = null stream).
+ * SV_ENOMEM if the state would not fit in free device memory (checked before
+ * any allocation). */
+int sv_alloc(int n_qubits, int dtype, void *dev_buf, void *hip_stream, sv_handle *out);
+
+/* Release the handle and whatever the library allocated for it. */
+int sv_free(sv_handle h);
+
+/* Set the state to the basis state |x> (x < 2^n). */
+int sv_set_basis(sv_handle h, uint64_t x);
+
+/* Rebind the handle to another HIP stream. */
+int sv_set_stream(sv_handle h, void *hip_stream);
+
+/* Wait for all work of the handle; SV_EDEVICE if a kernel failed. */
+int sv_sync(sv_handle h);
+
+/* Device pointer of the amplitudes. */
+void *sv_data(sv_handle h);
+
+/* Apply one k-qubit gate (k = 1 or 2) with optional controls: Alg. 1 of
+ * Sec. 2.3 for k = 1 (every pair of amplitudes that differ only in bit
+ * targets[0] is multiplied by U; with controls, only pairs whose control bits
+ * are all 1), and its 4x4 analogue on the quadruples differing in bits
+ * targets[0], targets[1] for k = 2.  Diagonal gates touch only the
+ * amplitudes they change.  SV_EINVAL for k outside {1,2}, a target or
+ * control >= n, duplicate targets, a control that is also a target, or NULL
+ * pointers. */
+int sv_apply_gate(sv_handle h, int k, const int *targets, uint64_t ctrl_mask, const double *U);
+
+/* Apply a dense k-qubit block (1 <= k <= 5), typically the product of
+ * several gates computed by sv_fuse: every group of 2^k amplitudes differing
+ * only in the bits qubits[0..k-1] is multiplied by U (bit j <-> qubits[j]).
+ * prec selects the arithmetic (enum sv_prec); SV_PREC_FP32 and
+ * SV_PREC_SPLIT_BF16 need k >= 4 and run on the matrix cores, and require an
+ * SV_C64 state.  SV_EUNSUPPORTED for other combinations. */
+int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int prec);
+
+/* Sec. 2.4: write p_x = re^2 + im^2 for every x to dev_out (float[2^n] for
+ * SV_C64, double[2^n] for SV_C128; device memory, may be NULL to skip the
+ * write) and, if host_norm is not NULL, the FP64 sum of all p_x. */
+int sv_probabilities(sv_handle h, void *dev_out, double *host_norm);
+
+/* <psi| sum_j coeffs[j] Z^{z_masks[j]} |psi> accumulated in FP64, where
+ * Z^m is the product of Pauli Z on the qubits of mask m (eigenvalue
+ * (-1)^popcount(x & m) on |x>).  1 <= n_terms <= 64. */
+int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const double *coeffs,
+                   double *host_out);
+
+/* Run a gate list on the state.  params (n_params doubles, may be NULL when
+ * no op has param_index >= 0) supplies the angles of parametrised ops.
+ * mode SV_RUN_PER_GATE launches one kernel per gate; SV_RUN_TILED lets the
+ * scheduler apply consecutive gates that act inside one tile of qubits in a
+ * single pass through on-chip memory, and stream the others. */
+enum sv_run_mode { SV_RUN_PER_GATE = 0, SV_RUN_TILED = 1 };
+int sv_run(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
+           int mode);
+
+/* Greedy fusion (host, FP64): walk ops in order, growing a block whose qubit
+ * set (targets and controls) has at most k_max qubits; multiply each gate
+ * into the block's 2^k x 2^k matrix; start a new block when a gate does not
+ * fit.  Writes up to max_blocks blocks: block_k[b], block_qubits[b*5 ..]
+ * (ascending, -1 padded), block_mats[b * 2*32*32 ..] (2^k x 2^k row-major
+ * interleaved, leading dimension 2^k), block_gates[b] (gates absorbed).
+ * *n_blocks receives the block count (SV_EINVAL if it exceeds max_blocks).
+ * 1 <= k_max <= 5. */
+int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int n_params,
+            int k_max, int max_blocks, int *block_k, int *block_qubits, double *block_mats,
+            int *block_gates, int *n_blocks);
+
+/* Fuse (as sv_fuse) and apply every block with sv_apply_fused(prec); blocks
+ * of fewer than 4 qubits use the native path.  *n_blocks_out (may be NULL)
+ * receives the number of blocks applied. */
+int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
+                 int k_max, int prec, int *n_blocks_out);
+
+/* Adjoint-method gradient of L = <psi| H |psi>, H = sum_j coeffs[j] Z^{z_masks[j]},
+ * psi = U_G ... U_1 psi_0 for the gate list ops with angles params.
+ * On entry h must hold the circuit's output psi (as left by sv_run with the
+ * same ops and params); lam is a second handle of the same size and dtype
+ * used as work space.  The reverse sweep undoes one gate at a time on psi and
+ * lam = H psi and accumulates dL/dtheta = 2 Re <lam| dU/dtheta |psi> for every
+ * parametrised gate in FP64.  Writes L to *host_loss and the n_params
+ * gradient entries to host_grad; on return h holds psi_0 as recovered by the
+ * sweep.  Parametrised ops must be RX, RY, RZ or U1 (controls allowed). */
+int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops,
+                    const double *params, int n_params, int n_terms, const uint64_t *z_masks,
+                    const double *coeffs, double *host_loss, double *host_grad);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sv_last_error(void);
+
+/* Library version string. */
+const char *sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_H */

@@ -1,0 +1,264 @@
+"""MI355X (gfx950) state-vector simulator: Python binding of libsv.so.
+
+Functions named after the C entry points marshal arguments (torch tensors
+for device memory and the current HIP stream, numpy arrays for host data)
+and call the library; every step of the simulation runs in the library's HIP
+kernels.  :class:`State` bundles a register's device buffer and handle.
+There is no CPU fallback: without the built library every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GATE_KINDS, SV_C64, SV_C128, SV_PREC_FP32, SV_PREC_NATIVE,
+                   SV_PREC_SPLIT_BF16, SV_RUN_PER_GATE, SV_RUN_TILED, SVError, sv_op)
+
+__all__ = ["State", "sv_alloc", "sv_free", "sv_set_basis", "sv_apply_gate", "sv_apply_fused",
+           "sv_probabilities", "sv_expectation", "sv_run", "sv_fuse", "sv_run_fused",
+           "sv_adjoint_grad", "sv_state_bytes", "ops_from_gates", "SV_C64", "SV_C128",
+           "SV_PREC_NATIVE", "SV_PREC_FP32", "SV_PREC_SPLIT_BF16", "SV_RUN_PER_GATE",
+           "SV_RUN_TILED", "SVError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _u64ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _current_stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (SV_C64, SV_C128):
+        return dtype
+    torch = _torch()
+    if dtype in ("c64", "complex64", torch.complex64, np.complex64):
+        return SV_C64
+    if dtype in ("c128", "complex128", torch.complex128, np.complex128):
+        return SV_C128
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+
+def sv_state_bytes(n_qubits: int, dtype) -> int:
+    return int(_lib.load().sv_state_bytes(n_qubits, _dtype_code(dtype)))
+
+
+def sv_alloc(n_qubits: int, dtype, dev_buf=None, stream=None) -> ctypes.c_void_p:
+    """Handle of an n-qubit register in |0..0>.  dev_buf: a CUDA tensor of
+    2^n complex elements to use as storage (kept alive by the caller)."""
+    h = ctypes.c_void_p()
+    ptr = ctypes.c_void_p(dev_buf.data_ptr()) if dev_buf is not None else None
+    s = stream if stream is not None else _current_stream()
+    _lib.check(_lib.load().sv_alloc(n_qubits, _dtype_code(dtype), ptr, s, ctypes.byref(h)))
+    return h
+
+
+def sv_free(h) -> None:
+    _lib.check(_lib.load().sv_free(h))
+
+
+def sv_set_basis(h, x: int) -> None:
+    _lib.check(_lib.load().sv_set_basis(h, int(x)))
+
+
+def sv_sync(h) -> None:
+    _lib.check(_lib.load().sv_sync(h))
+
+
+def _mat(U) -> np.ndarray:
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    return np.ascontiguousarray(U.view(np.float64).reshape(-1))
+
+
+def sv_apply_gate(h, targets: Sequence[int], U, ctrl_mask: int = 0) -> None:
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    m = _mat(U)
+    _lib.check(_lib.load().sv_apply_gate(h, len(t), _iptr(t), int(ctrl_mask), _dptr(m)))
+
+
+def sv_apply_fused(h, qubits: Sequence[int], U, prec: int = SV_PREC_NATIVE) -> None:
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    m = _mat(U)
+    _lib.check(_lib.load().sv_apply_fused(h, len(q), _iptr(q), _dptr(m), int(prec)))
+
+
+def sv_probabilities(h, out=None) -> float:
+    """Probabilities into ``out`` (CUDA float32/float64 tensor of 2^n, or
+    None) and the FP64 total."""
+    norm = ctypes.c_double()
+    ptr = ctypes.c_void_p(out.data_ptr()) if out is not None else None
+    _lib.check(_lib.load().sv_probabilities(h, ptr, ctypes.byref(norm)))
+    return norm.value
+
+
+def sv_expectation(h, z_masks: Sequence[int], coeffs: Sequence[float]) -> float:
+    m = np.ascontiguousarray(z_masks, dtype=np.uint64)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    out = ctypes.c_double()
+    _lib.check(_lib.load().sv_expectation(h, len(m), _u64ptr(m), _dptr(c), ctypes.byref(out)))
+    return out.value
+
+
+def ops_from_gates(gates) -> ctypes.Array:
+    """sv_op array from symbolic gates (name, targets, controls, theta,
+    param, matrix) as produced by the circuit generators."""
+    arr = (sv_op * max(1, len(gates)))()
+    for i, g in enumerate(gates):
+        op = arr[i]
+        op.kind = GATE_KINDS[g.name]
+        op.n_targets = len(g.targets)
+        for j, q in enumerate(g.targets[:2]):
+            op.targets[j] = q
+        mask = 0
+        for c in g.controls:
+            mask |= 1 << c
+        op.ctrl_mask = mask
+        op.param_index = g.param
+        op.theta = g.theta
+        if g.name == "U":
+            m = _mat(g.matrix)
+            if m.size > 32:
+                raise ValueError("sv_op holds at most a 4x4 matrix")
+            ctypes.memmove(op.matrix, m.ctypes.data, m.nbytes)
+    return arr
+
+
+def _params(params) -> tuple:
+    if params is None:
+        return None, 0, None
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    return _dptr(p), len(p), p
+
+
+def sv_run(h, gates, params=None, mode: int = SV_RUN_TILED) -> None:
+    ops = ops_from_gates(gates)
+    pp, n_p, keep = _params(params)
+    _lib.check(_lib.load().sv_run(h, ops, len(gates), pp, n_p, int(mode)))
+
+
+def sv_fuse(n_qubits: int, gates, k_max: int, params=None, max_blocks: Optional[int] = None):
+    """Greedy fusion on the host library: list of (qubits, 2^k x 2^k matrix,
+    number of gates absorbed)."""
+    ops = ops_from_gates(gates)
+    pp, n_p, keep = _params(params)
+    cap = max_blocks or max(1, len(gates))
+    bk = np.zeros(cap, np.int32)
+    bq = np.full(cap * 5, -1, np.int32)
+    bm = np.zeros(cap * 2 * 32 * 32, np.float64)
+    bg = np.zeros(cap, np.int32)
+    nb = ctypes.c_int()
+    _lib.check(_lib.load().sv_fuse(n_qubits, ops, len(gates), pp, n_p, k_max, cap, _iptr(bk),
+                                   _iptr(bq), _dptr(bm), _iptr(bg), ctypes.byref(nb)))
+    out = []
+    for b in range(nb.value):
+        k = int(bk[b])
+        d = 1 << k
+        m = bm[b * 2048:b * 2048 + 2 * d * d].view(np.complex128).reshape(d, d).copy()
+        out.append((tuple(int(q) for q in bq[b * 5:b * 5 + k]), m, int(bg[b])))
+    return out
+
+
+def sv_run_fused(h, gates, k_max: int, prec: int, params=None) -> int:
+    ops = ops_from_gates(gates)
+    pp, n_p, keep = _params(params)
+    nb = ctypes.c_int()
+    _lib.check(_lib.load().sv_run_fused(h, ops, len(gates), pp, n_p, int(k_max), int(prec),
+                                        ctypes.byref(nb)))
+    return nb.value
+
+
+def sv_adjoint_grad(h, lam, gates, params, z_masks, coeffs):
+    ops = ops_from_gates(gates)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    m = np.ascontiguousarray(z_masks, dtype=np.uint64)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    grad = np.zeros(len(p), np.float64)
+    loss = ctypes.c_double()
+    _lib.check(_lib.load().sv_adjoint_grad(h, lam, ops, len(gates), _dptr(p), len(p), len(m),
+                                           _u64ptr(m), _dptr(c), ctypes.byref(loss), _dptr(grad)))
+    return loss.value, grad
+
+
+# ------------------------------------------------------------------ State
+
+class State:
+    """An n-qubit register whose amplitudes live in a torch CUDA tensor."""
+
+    def __init__(self, n_qubits: int, dtype="c128", device=None):
+        torch = _torch()
+        code = _dtype_code(dtype)
+        self.n = n_qubits
+        self.dtype = code
+        tdt = torch.complex64 if code == SV_C64 else torch.complex128
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(dev):
+            self.amps = torch.empty(1 << n_qubits, dtype=tdt, device=dev)
+            self.handle = sv_alloc(n_qubits, code, self.amps, _current_stream())
+        self.device = dev
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            sv_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_basis(self, x: int) -> "State":
+        sv_set_basis(self.handle, x)
+        return self
+
+    def apply(self, U, targets, controls: Iterable[int] = ()) -> "State":
+        mask = 0
+        for c in controls:
+            mask |= 1 << c
+        sv_apply_gate(self.handle, list(targets), U, mask)
+        return self
+
+    def apply_fused(self, U, qubits, prec: int = SV_PREC_NATIVE) -> "State":
+        sv_apply_fused(self.handle, list(qubits), U, prec)
+        return self
+
+    def run(self, gates, params=None, mode: int = SV_RUN_TILED) -> "State":
+        sv_run(self.handle, gates, params, mode)
+        return self
+
+    def run_fused(self, gates, k_max: int = 5, prec: int = SV_PREC_FP32, params=None) -> int:
+        return sv_run_fused(self.handle, gates, k_max, prec, params)
+
+    def probabilities(self, out=None) -> float:
+        return sv_probabilities(self.handle, out)
+
+    def expectation(self, z_masks, coeffs) -> float:
+        return sv_expectation(self.handle, z_masks, coeffs)
+
+    def sync(self) -> "State":
+        sv_sync(self.handle)
+        return self
+
+    def numpy(self) -> np.ndarray:
+        self.sync()
+        return self.amps.cpu().numpy()

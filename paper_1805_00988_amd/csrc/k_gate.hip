@@ -1,0 +1,469 @@
+// Gate kernels: streamed pair/quad updates for gates on high qubits, a
+// subspace-scaling kernel for phase-type diagonal gates, and the on-chip tile
+// pass that applies a run of gates to tiles staged in LDS.
+//
+// Memory access: the state is read and written as 16-byte vectors (float4 =
+// two complex64 amplitudes, double2 = one complex128 amplitude).  Consecutive
+// lanes take consecutive vectors of the same half of the pair space, so every
+// wavefront load is a contiguous run as long as the target qubit is above the
+// vector width.
+#include "sv_internal.hpp"
+
+#include <algorithm>
+
+namespace sv {
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+    using type = float4;
+    static constexpr int amps = 2;
+    static constexpr int bits = 1;
+    __device__ static cpx<float> get(const float4 &v, int k) {
+        return k == 0 ? cpx<float>{v.x, v.y} : cpx<float>{v.z, v.w};
+    }
+    __device__ static void put(float4 &v, int k, cpx<float> c) {
+        if (k == 0) { v.x = c.re; v.y = c.im; } else { v.z = c.re; v.w = c.im; }
+    }
+};
+template <>
+struct Vec<double> {
+    using type = double2;
+    static constexpr int amps = 1;
+    static constexpr int bits = 0;
+    __device__ static cpx<double> get(const double2 &v, int) { return {v.x, v.y}; }
+    __device__ static void put(double2 &v, int, cpx<double> c) { v.x = c.re; v.y = c.im; }
+};
+
+constexpr int kStreamThreads = 256;
+
+static inline uint64_t grid_for(uint64_t work_items, uint64_t per_block, uint64_t cap) {
+    uint64_t b = (work_items + per_block - 1) / per_block;
+    return std::max<uint64_t>(1, std::min<uint64_t>(b, cap));
+}
+
+// ---------------------------------------------------------------- init
+template <typename T>
+__global__ __launch_bounds__(kStreamThreads) void k_init_basis(typename Vec<T>::type *v,
+                                                               uint64_t n_vec, uint64_t x) {
+    using V = Vec<T>;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_vec; e += stride) {
+        typename V::type z;
+        for (int k = 0; k < V::amps; ++k)
+            V::put(z, k, cpx<T>{(((e << V::bits) | k) == x) ? T(1) : T(0), T(0)});
+        v[e] = z;
+    }
+}
+
+hipError_t launch_init_basis(void *amps, int n, int dtype, uint64_t x, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    if (dtype == SV_C64) {
+        const uint64_t nv = N / 2;
+        k_init_basis<float><<<dim3((unsigned)grid_for(nv, kStreamThreads, 65536)), dim3(kStreamThreads), 0, s>>>((float4 *)amps, nv, x);
+    } else {
+        k_init_basis<double><<<dim3((unsigned)grid_for(N, kStreamThreads, 65536)), dim3(kStreamThreads), 0, s>>>((double2 *)amps, N, x);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- streamed 1q gate
+// Element-pair j -> element a (bit te clear, control bits set) and a | 2^te.
+// lane_ctrl holds control bits below the vector width (amplitude bits inside
+// one 16-byte element): only amplitudes with all of them set are updated.
+template <typename T, int UNROLL>
+__global__ __launch_bounds__(kStreamThreads) void k_gate1(typename Vec<T>::type *v, Enum e, int te,
+                                                          uint64_t count, Mat2<T> g,
+                                                          uint32_t lane_ctrl) {
+    using V = Vec<T>;
+    const uint64_t per_block = (uint64_t)UNROLL * kStreamThreads;
+    const uint64_t bstep = 1ull << te;
+    for (uint64_t base = (uint64_t)blockIdx.x * per_block; base < count;
+         base += (uint64_t)gridDim.x * per_block) {
+        typename V::type va[UNROLL], vb[UNROLL];
+        uint64_t ia[UNROLL];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t j = base + (uint64_t)u * kStreamThreads + threadIdx.x;
+            const uint64_t a = expand(e, j < count ? j : 0);
+            ok[u] = (j < count) && ((a & e.check) == e.check);
+            ia[u] = a;
+            if (ok[u]) {
+                va[u] = v[a];
+                vb[u] = v[a + bstep];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (!ok[u]) continue;
+            typename V::type oa = va[u], ob = vb[u];
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) {
+                if (((uint32_t)k & lane_ctrl) != lane_ctrl) continue;
+                const cpx<T> x0 = V::get(va[u], k), x1 = V::get(vb[u], k);
+                V::put(oa, k, cfma(g.m[0], x0, cmul(g.m[1], x1)));
+                V::put(ob, k, cfma(g.m[2], x0, cmul(g.m[3], x1)));
+            }
+            v[ia[u]] = oa;
+            v[ia[u] + bstep] = ob;
+        }
+    }
+}
+
+// complex64 gate on qubit 0: both amplitudes of a pair sit in one float4.
+template <int UNROLL>
+__global__ __launch_bounds__(kStreamThreads) void k_gate1_q0(float4 *v, Enum e, uint64_t count,
+                                                             Mat2<float> g) {
+    const uint64_t per_block = (uint64_t)UNROLL * kStreamThreads;
+    for (uint64_t base = (uint64_t)blockIdx.x * per_block; base < count;
+         base += (uint64_t)gridDim.x * per_block) {
+        float4 w[UNROLL];
+        uint64_t ia[UNROLL];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t j = base + (uint64_t)u * kStreamThreads + threadIdx.x;
+            const uint64_t a = expand(e, j < count ? j : 0);
+            ok[u] = (j < count) && ((a & e.check) == e.check);
+            ia[u] = a;
+            if (ok[u]) w[u] = v[a];
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (!ok[u]) continue;
+            const cpx<float> x0{w[u].x, w[u].y}, x1{w[u].z, w[u].w};
+            const cpx<float> y0 = cfma(g.m[0], x0, cmul(g.m[1], x1));
+            const cpx<float> y1 = cfma(g.m[2], x0, cmul(g.m[3], x1));
+            v[ia[u]] = float4{y0.re, y0.im, y1.re, y1.im};
+        }
+    }
+}
+
+// Build the element-level enumeration for a set of zero positions (element
+// bit indices) plus control bits; controls beyond the insert capacity are
+// checked instead of enumerated.
+static Enum make_enum(int vbits, const int *zero_pos, int n_zero, uint64_t ctrl,
+                      uint32_t *lane_ctrl, int *n_enumerated) {
+    Enum e{};
+    int pos[64];
+    int np = 0;
+    for (int i = 0; i < n_zero; ++i) pos[np++] = zero_pos[i];
+    const uint64_t lane_mask = (1ull << vbits) - 1ull;
+    *lane_ctrl = (uint32_t)(ctrl & lane_mask);
+    uint64_t ec = ctrl >> vbits;
+    e.set = 0;
+    e.check = 0;
+    while (ec) {
+        const int b = __builtin_ctzll(ec);
+        ec &= ec - 1;
+        if (np < kMaxInsert) {
+            pos[np++] = b;
+            e.set |= 1ull << b;
+        } else {
+            e.check |= 1ull << b;
+        }
+    }
+    std::sort(pos, pos + np);
+    e.n_pos = np;
+    for (int i = 0; i < np; ++i) e.pos[i] = pos[i];
+    *n_enumerated = np;
+    return e;
+}
+
+template <typename T>
+static Mat2<T> to_mat2(const double *U) {
+    Mat2<T> g;
+    for (int i = 0; i < 4; ++i) g.m[i] = cpx<T>{(T)U[2 * i], (T)U[2 * i + 1]};
+    return g;
+}
+
+constexpr int kUnroll = 4;
+constexpr uint64_t kGridCap = 1ull << 20;
+
+hipError_t launch_gate1(void *amps, int n, int dtype, int t, uint64_t ctrl, const double *U,
+                        hipStream_t s) {
+    const int vbits = dtype == SV_C64 ? 1 : 0;
+    const uint64_t n_el = (1ull << n) >> vbits;
+    uint32_t lane_ctrl = 0;
+    int np = 0;
+    if (t < vbits) {
+        // complex64, target qubit 0: enumerate elements restricted by controls
+        Enum e = make_enum(vbits, nullptr, 0, ctrl, &lane_ctrl, &np);
+        const uint64_t count = n_el >> np;
+        const uint64_t per = (uint64_t)kUnroll * kStreamThreads;
+        k_gate1_q0<kUnroll><<<dim3((unsigned)grid_for(count, per, kGridCap)), dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, to_mat2<float>(U));
+        return hipGetLastError();
+    }
+    const int te = t - vbits;
+    Enum e = make_enum(vbits, &te, 1, ctrl, &lane_ctrl, &np);
+    const uint64_t count = n_el >> np;
+    const uint64_t per = (uint64_t)kUnroll * kStreamThreads;
+    const dim3 grid((unsigned)grid_for(count, per, kGridCap));
+    if (dtype == SV_C64)
+        k_gate1<float, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te, count, to_mat2<float>(U), lane_ctrl);
+    else
+        k_gate1<double, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te, count, to_mat2<double>(U), lane_ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- streamed 2q gate
+// Quad index q = b0 + 2 b1 (bit j of q = value of targets[j]); both targets
+// at or above the vector width.
+template <typename T, int UNROLL>
+__global__ __launch_bounds__(kStreamThreads) void k_gate2(typename Vec<T>::type *v, Enum e, int te0,
+                                                          int te1, uint64_t count, Mat4<T> g,
+                                                          uint32_t lane_ctrl) {
+    using V = Vec<T>;
+    const uint64_t per_block = (uint64_t)UNROLL * kStreamThreads;
+    const uint64_t s0 = 1ull << te0, s1 = 1ull << te1;
+    for (uint64_t base = (uint64_t)blockIdx.x * per_block; base < count;
+         base += (uint64_t)gridDim.x * per_block) {
+        typename V::type w[UNROLL][4];
+        uint64_t ia[UNROLL];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t j = base + (uint64_t)u * kStreamThreads + threadIdx.x;
+            const uint64_t a = expand(e, j < count ? j : 0);
+            ok[u] = (j < count) && ((a & e.check) == e.check);
+            ia[u] = a;
+            if (ok[u]) {
+                w[u][0] = v[a];
+                w[u][1] = v[a + s0];
+                w[u][2] = v[a + s1];
+                w[u][3] = v[a + s0 + s1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (!ok[u]) continue;
+            typename V::type o[4] = {w[u][0], w[u][1], w[u][2], w[u][3]};
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) {
+                if (((uint32_t)k & lane_ctrl) != lane_ctrl) continue;
+                cpx<T> x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = V::get(w[u][q], k);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cpx<T> acc = cmul(g.m[4 * r], x[0]);
+#pragma unroll
+                    for (int c = 1; c < 4; ++c) acc = cfma(g.m[4 * r + c], x[c], acc);
+                    V::put(o[r], k, acc);
+                }
+            }
+            v[ia[u]] = o[0];
+            v[ia[u] + s0] = o[1];
+            v[ia[u] + s1] = o[2];
+            v[ia[u] + s0 + s1] = o[3];
+        }
+    }
+}
+
+template <typename T>
+static Mat4<T> to_mat4(const double *U) {
+    Mat4<T> g;
+    for (int i = 0; i < 16; ++i) g.m[i] = cpx<T>{(T)U[2 * i], (T)U[2 * i + 1]};
+    return g;
+}
+
+hipError_t launch_gate2(void *amps, int n, int dtype, int t0, int t1, uint64_t ctrl,
+                        const double *U, hipStream_t s) {
+    const int vbits = dtype == SV_C64 ? 1 : 0;
+    if (t0 < vbits || t1 < vbits) return hipErrorInvalidValue; // routed to the tile pass
+    const uint64_t n_el = (1ull << n) >> vbits;
+    const int te[2] = {t0 - vbits, t1 - vbits};
+    uint32_t lane_ctrl = 0;
+    int np = 0;
+    Enum e = make_enum(vbits, te, 2, ctrl, &lane_ctrl, &np);
+    const uint64_t count = n_el >> np;
+    constexpr int U2 = 2;
+    const uint64_t per = (uint64_t)U2 * kStreamThreads;
+    const dim3 grid((unsigned)grid_for(count, per, kGridCap));
+    if (dtype == SV_C64)
+        k_gate2<float, U2><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te[0], te[1], count, to_mat4<float>(U), lane_ctrl);
+    else
+        k_gate2<double, U2><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te[0], te[1], count, to_mat4<double>(U), lane_ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- subspace scaling
+// Multiply every amplitude x with (x & mask) == mask by a complex factor:
+// a phase-type diagonal gate (diag(1, f), optionally controlled) only changes
+// the amplitudes whose target and control bits are all 1.
+template <typename T, int UNROLL>
+__global__ __launch_bounds__(kStreamThreads) void k_scale(typename Vec<T>::type *v, Enum e,
+                                                          uint64_t count, cpx<T> f,
+                                                          uint32_t lane_set) {
+    using V = Vec<T>;
+    const uint64_t per_block = (uint64_t)UNROLL * kStreamThreads;
+    for (uint64_t base = (uint64_t)blockIdx.x * per_block; base < count;
+         base += (uint64_t)gridDim.x * per_block) {
+        typename V::type w[UNROLL];
+        uint64_t ia[UNROLL];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t j = base + (uint64_t)u * kStreamThreads + threadIdx.x;
+            const uint64_t a = expand(e, j < count ? j : 0);
+            ok[u] = (j < count) && ((a & e.check) == e.check);
+            ia[u] = a;
+            if (ok[u]) w[u] = v[a];
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) {
+                if (((uint32_t)k & lane_set) != lane_set) continue;
+                V::put(w[u], k, cmul(f, V::get(w[u], k)));
+            }
+            v[ia[u]] = w[u];
+        }
+    }
+}
+
+hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const double *factor,
+                        hipStream_t s) {
+    const int vbits = dtype == SV_C64 ? 1 : 0;
+    const uint64_t n_el = (1ull << n) >> vbits;
+    uint32_t lane_set = 0;
+    int np = 0;
+    Enum e = make_enum(vbits, nullptr, 0, set_mask, &lane_set, &np);
+    const uint64_t count = n_el >> np;
+    const uint64_t per = (uint64_t)kUnroll * kStreamThreads;
+    const dim3 grid((unsigned)grid_for(count, per, kGridCap));
+    if (dtype == SV_C64)
+        k_scale<float, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, cpx<float>{(float)factor[0], (float)factor[1]}, lane_set);
+    else
+        k_scale<double, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, count, cpx<double>{factor[0], factor[1]}, lane_set);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ tile pass
+// A workgroup stages one tile of 2^m amplitudes in LDS: the low qubits
+// 0..L-1 (contiguous runs of 2^L amplitudes in HBM) plus K further qubits.
+// Every gate of the pass acts on tile qubits only; controls outside the tile
+// are constant over a tile and are tested once on its base index.
+constexpr int kTileThreads = 512;
+
+int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; } // 64 KiB of LDS
+
+template <typename T>
+__device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t base, uint32_t l) {
+    uint64_t g = base | (l & ((1u << sp.L) - 1u));
+    uint32_t hi = l >> sp.L;
+#pragma unroll
+    for (int i = 0; i < kMaxTileHigh; ++i) {
+        if (i >= sp.K) break;
+        if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
+    }
+    return g;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> gm(const TileGate &G, int i) {
+    return cpx<T>{(T)G.m[2 * i], (T)G.m[2 * i + 1]};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v, TileSpec sp, int m,
+                                                       const TileGate *__restrict__ gates,
+                                                       int n_gates, uint64_t n_tiles) {
+    using V = Vec<T>;
+    extern __shared__ char lds_raw[];
+    cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
+    const uint32_t tsize = 1u << m;
+    const uint32_t tvec = tsize >> V::bits;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint64_t base = tile << sp.L;
+        for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
+        // stage in: element l covers local amplitudes l*VA .. l*VA+VA-1 (L >= vector bits)
+        for (uint32_t l = threadIdx.x; l < tvec; l += kTileThreads) {
+            const uint32_t la = l << V::bits;
+            const typename V::type w = v[tile_global<T>(sp, base, la) >> V::bits];
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) lds[la + k] = V::get(w, k);
+        }
+        __syncthreads();
+        for (int gi = 0; gi < n_gates; ++gi) {
+            const TileGate &G = gates[gi];
+            if ((base & G.cout) != G.cout) continue; // uniform over the workgroup
+            const uint32_t cin = G.cin;
+            if (G.kind == TG_1Q) {
+                const cpx<T> g0 = gm<T>(G, 0), g1 = gm<T>(G, 1), g2 = gm<T>(G, 2), g3 = gm<T>(G, 3);
+                const int b = G.b0;
+                const uint32_t low = (1u << b) - 1u;
+                for (uint32_t p = threadIdx.x; p < (tsize >> 1); p += kTileThreads) {
+                    const uint32_t a = (p & low) | ((p & ~low) << 1);
+                    if ((a & cin) != cin) continue;
+                    const uint32_t c = a | (1u << b);
+                    const cpx<T> x0 = lds[a], x1 = lds[c];
+                    lds[a] = cfma(g0, x0, cmul(g1, x1));
+                    lds[c] = cfma(g2, x0, cmul(g3, x1));
+                }
+            } else if (G.kind == TG_2Q) {
+                const int b0 = G.b0, b1 = G.b1;
+                const int lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
+                const uint32_t mlo = (1u << lo) - 1u, mhi = (1u << hi) - 1u;
+                for (uint32_t p = threadIdx.x; p < (tsize >> 2); p += kTileThreads) {
+                    uint32_t a = (p & mlo) | ((p & ~mlo) << 1);
+                    a = (a & mhi) | ((a & ~mhi) << 1);
+                    if ((a & cin) != cin) continue;
+                    uint32_t idx[4] = {a, a | (1u << b0), a | (1u << b1), a | (1u << b0) | (1u << b1)};
+                    cpx<T> x[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) x[q] = lds[idx[q]];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        cpx<T> acc = cmul(gm<T>(G, 4 * r), x[0]);
+#pragma unroll
+                        for (int c = 1; c < 4; ++c) acc = cfma(gm<T>(G, 4 * r + c), x[c], acc);
+                        lds[idx[r]] = acc;
+                    }
+                }
+            } else { // TG_DIAG: amplitude *= d0 (bit b0 clear) or d1 (bit b0 set)
+                const cpx<T> d0 = gm<T>(G, 0), d1 = gm<T>(G, 1);
+                const int b = G.b0;
+                for (uint32_t l = threadIdx.x; l < tsize; l += kTileThreads) {
+                    if ((l & cin) != cin) continue;
+                    lds[l] = cmul(((l >> b) & 1u) ? d1 : d0, lds[l]);
+                }
+            }
+            __syncthreads();
+        }
+        for (uint32_t l = threadIdx.x; l < tvec; l += kTileThreads) {
+            const uint32_t la = l << V::bits;
+            typename V::type w;
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) V::put(w, k, lds[la + k]);
+            v[tile_global<T>(sp, base, la) >> V::bits] = w;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileGate *dev_gates,
+                       int n_gates, hipStream_t s) {
+    const int m = spec.L + spec.K;
+    const int vbits = dtype == SV_C64 ? 1 : 0;
+    if (m > n || m > tile_max_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh)
+        return hipErrorInvalidValue;
+    const uint64_t n_tiles = 1ull << (n - m);
+    const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
+    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 2048);
+    if (dtype == SV_C64) {
+        (void)hipFuncSetAttribute((const void *)k_tile<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        k_tile<float><<<dim3(grid), dim3(kTileThreads), lds, s>>>((float4 *)amps, spec, m, dev_gates, n_gates, n_tiles);
+    } else {
+        (void)hipFuncSetAttribute((const void *)k_tile<double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_tile<double><<<dim3(grid), dim3(kTileThreads), lds, s>>>((double2 *)amps, spec, m, dev_gates, n_gates, n_tiles);
+    }
+    return hipGetLastError();
+}
+
+} // namespace sv

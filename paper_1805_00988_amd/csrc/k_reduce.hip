@@ -1,0 +1,166 @@
+// Reductions over the state: measurement probabilities (Sec. 2.4) with the
+// FP64 total, and Z-string expectation values accumulated in FP64.
+//
+// Both kernels stream the state once with 16-byte loads, keep one FP64
+// partial sum per lane, reduce a wavefront with cross-lane shuffles and a
+// workgroup through LDS, and write one partial per workgroup; a one-block
+// kernel adds the partials in a fixed order, so results are deterministic.
+#include "sv_internal.hpp"
+
+#include <algorithm>
+
+namespace sv {
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+    x = wave_sum(x);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = x;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_sum_partials(const double *partials, int n,
+                                                              double *total) {
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRedThreads) acc += partials[i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) *total = acc;
+}
+
+// complex64: one float4 = amplitudes 2e, 2e+1 -> probabilities as float2.
+__global__ __launch_bounds__(kRedThreads) void k_probs_c64(const float4 *__restrict__ v,
+                                                           uint64_t n_vec, float2 *__restrict__ out,
+                                                           double *partials) {
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
+    for (uint64_t e = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n_vec; e += stride) {
+        const float4 w = v[e];
+        const float p0 = fmaf(w.x, w.x, w.y * w.y), p1 = fmaf(w.z, w.z, w.w * w.w);
+        if (out) out[e] = float2{p0, p1};
+        acc += (double)w.x * w.x + (double)w.y * w.y + (double)w.z * w.z + (double)w.w * w.w;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_probs_c128(const double2 *__restrict__ v,
+                                                            uint64_t n, double *__restrict__ out,
+                                                            double *partials) {
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
+    for (uint64_t e = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
+        const double2 w = v[e];
+        const double p = fma(w.x, w.x, w.y * w.y);
+        if (out) out[e] = p;
+        acc += p;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+static unsigned red_grid(uint64_t work, int n_partials) {
+    uint64_t b = (work + kRedThreads - 1) / kRedThreads;
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, (uint64_t)n_partials));
+}
+
+hipError_t launch_probabilities(const void *amps, int n, int dtype, void *dev_out,
+                                double *dev_partials, int n_partials, double *dev_total,
+                                hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    unsigned grid;
+    if (dtype == SV_C64) {
+        grid = red_grid(N / 2, n_partials);
+        k_probs_c64<<<dim3(grid), dim3(kRedThreads), 0, s>>>((const float4 *)amps, N / 2, (float2 *)dev_out, dev_partials);
+    } else {
+        grid = red_grid(N, n_partials);
+        k_probs_c128<<<dim3(grid), dim3(kRedThreads), 0, s>>>((const double2 *)amps, N, (double *)dev_out, dev_partials);
+    }
+    k_sum_partials<<<dim3(1), dim3(kRedThreads), 0, s>>>(dev_partials, (int)grid, dev_total);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- expectation
+struct Terms {
+    int n;
+    uint64_t mask[kMaxTerms];
+    double coeff[kMaxTerms];
+};
+
+__device__ __forceinline__ double zsum(const Terms &t, uint64_t x) {
+    double h = 0.0;
+    for (int j = 0; j < t.n; ++j) {
+        const double c = t.coeff[j];
+        h += (__popcll(x & t.mask[j]) & 1) ? -c : c;
+    }
+    return h;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_expect_c64(const float4 *__restrict__ v,
+                                                            uint64_t n_vec, Terms t,
+                                                            double *partials) {
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
+    for (uint64_t e = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n_vec; e += stride) {
+        const float4 w = v[e];
+        const double p0 = (double)w.x * w.x + (double)w.y * w.y;
+        const double p1 = (double)w.z * w.z + (double)w.w * w.w;
+        acc += p0 * zsum(t, 2 * e) + p1 * zsum(t, 2 * e + 1);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_expect_c128(const double2 *__restrict__ v,
+                                                             uint64_t n, Terms t,
+                                                             double *partials) {
+    __shared__ double sh[kRedThreads / 64];
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRedThreads;
+    for (uint64_t e = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += stride) {
+        const double2 w = v[e];
+        acc += fma(w.x, w.x, w.y * w.y) * zsum(t, e);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+hipError_t launch_expectation(const void *amps, int n, int dtype, int n_terms,
+                              const uint64_t *masks, const double *coeffs, double *dev_partials,
+                              int n_partials, double *dev_total, hipStream_t s) {
+    if (n_terms < 1 || n_terms > kMaxTerms) return hipErrorInvalidValue;
+    Terms t{};
+    t.n = n_terms;
+    for (int j = 0; j < n_terms; ++j) {
+        t.mask[j] = masks[j];
+        t.coeff[j] = coeffs[j];
+    }
+    const uint64_t N = 1ull << n;
+    unsigned grid;
+    if (dtype == SV_C64) {
+        grid = red_grid(N / 2, n_partials);
+        k_expect_c64<<<dim3(grid), dim3(kRedThreads), 0, s>>>((const float4 *)amps, N / 2, t, dev_partials);
+    } else {
+        grid = red_grid(N, n_partials);
+        k_expect_c128<<<dim3(grid), dim3(kRedThreads), 0, s>>>((const double2 *)amps, N, t, dev_partials);
+    }
+    k_sum_partials<<<dim3(1), dim3(kRedThreads), 0, s>>>(dev_partials, (int)grid, dev_total);
+    return hipGetLastError();
+}
+
+} // namespace sv

@@ -1,0 +1,566 @@
+// Host side of libsv.so: argument validation, state handles, the gate table
+// for sv_op records, single-gate dispatch, the tile-pass scheduler of sv_run,
+// and the reductions' host results.
+#include "sv_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+struct sv_state {
+    int n = 0;
+    int dtype = 0;
+    void *amps = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double *d_red = nullptr;          // kReduceBlocks partials + 1 total
+    double *h_result = nullptr;       // pinned, 8 doubles
+    sv::TileGate *d_gates = nullptr;  // tile-pass gate records
+    size_t gates_cap = 0;
+    sv::TileGate *h_gates = nullptr;  // pinned staging for d_gates
+    hipEvent_t stage_done = nullptr;  // last copy out of h_gates
+    bool stage_pending = false;
+};
+
+namespace sv {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *where) {
+    return fail(SV_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define SV_HIP(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);                                          \
+    } while (0)
+
+// ------------------------------------------------------------ gate table
+// H X Y Z S T per the gate table of Sec. 1.3.2; rotations exp(-i theta P/2);
+// U1 = diag(1, e^{i theta}).  Output: 4 complex entries, row-major, (re, im).
+static bool named_matrix(int kind, double th, double *U) {
+    const double c = std::cos(0.5 * th), s = std::sin(0.5 * th);
+    const double h = 0.70710678118654752440;
+    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    switch (kind) {
+    case SV_GATE_H: m[0] = h; m[2] = h; m[4] = h; m[6] = -h; break;
+    case SV_GATE_X: m[2] = 1; m[4] = 1; break;
+    case SV_GATE_Y: m[3] = -1; m[5] = 1; break;
+    case SV_GATE_Z: m[0] = 1; m[6] = -1; break;
+    case SV_GATE_S: m[0] = 1; m[7] = 1; break;
+    case SV_GATE_T: m[0] = 1; m[6] = h; m[7] = h; break;
+    case SV_GATE_RX: m[0] = c; m[3] = -s; m[5] = -s; m[6] = c; break;
+    case SV_GATE_RY: m[0] = c; m[2] = -s; m[4] = s; m[6] = c; break;
+    case SV_GATE_RZ: m[0] = c; m[1] = -s; m[6] = c; m[7] = s; break;
+    case SV_GATE_U1: m[0] = 1; m[6] = std::cos(th); m[7] = std::sin(th); break;
+    default: return false;
+    }
+    std::memcpy(U, m, sizeof(m));
+    return true;
+}
+
+// A gate in canonical form: k targets, controls, 2^k x 2^k matrix.
+struct Gate {
+    int k;
+    int t[2];
+    uint64_t ctrl;
+    double U[32];
+    uint64_t tmask() const { return (1ull << t[0]) | (k == 2 ? (1ull << t[1]) : 0ull); }
+    uint64_t qmask() const { return tmask() | ctrl; }
+};
+
+static int check_gate(int n, int k, const int *targets, uint64_t ctrl, const double *U) {
+    if (!targets || !U) return fail(SV_EINVAL, "NULL targets or matrix");
+    if (k != 1 && k != 2) return fail(SV_EINVAL, "k must be 1 or 2");
+    uint64_t seen = 0;
+    for (int j = 0; j < k; ++j) {
+        if (targets[j] < 0 || targets[j] >= n)
+            return fail(SV_EINVAL, "target qubit " + std::to_string(targets[j]) + " outside [0, n)");
+        if (seen & (1ull << targets[j])) return fail(SV_EINVAL, "duplicate target qubits");
+        seen |= 1ull << targets[j];
+    }
+    if (n < 64 && (ctrl >> n) != 0) return fail(SV_EINVAL, "control mask has bits >= n");
+    if (ctrl & seen) return fail(SV_EINVAL, "a control qubit is also a target");
+    for (int i = 0; i < 2 * (1 << (2 * k)); ++i)
+        if (!std::isfinite(U[i])) return fail(SV_EINVAL, "matrix entry is not finite");
+    return SV_OK;
+}
+
+static int op_to_gate(int n, const sv_op &op, const double *params, int n_params, Gate *g) {
+    double th = op.theta;
+    if (op.param_index >= 0) {
+        if (!params || op.param_index >= n_params)
+            return fail(SV_EINVAL, "param_index outside the parameter vector");
+        th = params[op.param_index];
+    }
+    g->ctrl = op.ctrl_mask;
+    if (op.kind == SV_GATE_MATRIX) {
+        if (op.n_targets != 1 && op.n_targets != 2)
+            return fail(SV_EINVAL, "matrix op needs 1 or 2 targets");
+        g->k = op.n_targets;
+        g->t[0] = op.targets[0];
+        g->t[1] = op.n_targets == 2 ? op.targets[1] : -1;
+        std::memcpy(g->U, op.matrix, sizeof(double) * 2 * (1 << (2 * g->k)));
+    } else {
+        if (op.n_targets != 1) return fail(SV_EINVAL, "named gates take one target");
+        g->k = 1;
+        g->t[0] = op.targets[0];
+        g->t[1] = -1;
+        if (!named_matrix(op.kind, th, g->U))
+            return fail(SV_EINVAL, "unknown gate kind " + std::to_string(op.kind));
+    }
+    return check_gate(n, g->k, g->t, g->ctrl, g->U);
+}
+
+// ---------------------------------------------------------------- buffers
+static int ensure_gate_capacity(sv_state *h, size_t count) {
+    if (count <= h->gates_cap) return SV_OK;
+    size_t cap = std::max<size_t>(64, h->gates_cap);
+    while (cap < count) cap *= 2;
+    if (h->stage_pending) SV_HIP(hipEventSynchronize(h->stage_done));
+    // the old device buffer may still be read by queued kernels: drain first
+    SV_HIP(hipStreamSynchronize(h->stream));
+    h->stage_pending = false;
+    if (h->d_gates) SV_HIP(hipFree(h->d_gates));
+    if (h->h_gates) SV_HIP(hipHostFree(h->h_gates));
+    h->d_gates = nullptr;
+    h->h_gates = nullptr;
+    h->gates_cap = 0;
+    SV_HIP(hipMalloc((void **)&h->d_gates, cap * sizeof(TileGate)));
+    SV_HIP(hipHostMalloc((void **)&h->h_gates, cap * sizeof(TileGate), hipHostMallocDefault));
+    h->gates_cap = cap;
+    return SV_OK;
+}
+
+// Copy staged gate records to the device on the handle's stream.  Kernels
+// queued earlier that read d_gates finish before the copy (stream order).
+static int upload_gates(sv_state *h, size_t count) {
+    SV_HIP(hipMemcpyAsync(h->d_gates, h->h_gates, count * sizeof(TileGate), hipMemcpyHostToDevice,
+                          h->stream));
+    SV_HIP(hipEventRecord(h->stage_done, h->stream));
+    h->stage_pending = true;
+    return SV_OK;
+}
+
+static int stage_wait(sv_state *h) {
+    if (h->stage_pending) SV_HIP(hipEventSynchronize(h->stage_done));
+    h->stage_pending = false;
+    return SV_OK;
+}
+
+// ------------------------------------------------------- single-gate path
+static bool is_one(const double *z) { return z[0] == 1.0 && z[1] == 0.0; }
+static bool is_zero(const double *z) { return z[0] == 0.0 && z[1] == 0.0; }
+
+static int vbits_of(int dtype) { return dtype == SV_C64 ? 1 : 0; }
+
+// Tile pass holding one gate (used for two-qubit gates on qubit 0 of a
+// complex64 state, whose pair partner is inside a 16-byte vector).
+static int tile_single(sv_state *h, const Gate &g);
+
+static int apply_one(sv_state *h, const Gate &g) {
+    if (g.k == 1) {
+        const double *U = g.U;
+        if (is_zero(U + 2) && is_zero(U + 4)) {
+            if (is_one(U) && is_one(U + 6)) return SV_OK; // identity
+            if (is_one(U)) {
+                SV_HIP(launch_scale(h->amps, h->n, h->dtype, g.ctrl | (1ull << g.t[0]), U + 6,
+                                    h->stream));
+                return SV_OK;
+            }
+        }
+        SV_HIP(launch_gate1(h->amps, h->n, h->dtype, g.t[0], g.ctrl, g.U, h->stream));
+        return SV_OK;
+    }
+    const int vb = vbits_of(h->dtype);
+    if (g.t[0] >= vb && g.t[1] >= vb) {
+        SV_HIP(launch_gate2(h->amps, h->n, h->dtype, g.t[0], g.t[1], g.ctrl, g.U, h->stream));
+        return SV_OK;
+    }
+    return tile_single(h, g);
+}
+
+// ------------------------------------------------------------- tile passes
+struct Pass {
+    std::vector<int> gates; // indices into the gate list, in application order
+    uint64_t S = 0;         // qubits staged in the tile
+};
+
+static void tile_layout(int n, int mmax, int lmin, uint64_t needed, TileSpec *sp) {
+    // low block of L >= lmin qubits plus the needed qubits above it; the
+    // scheduler guarantees lmin + popcount(needed >> lmin) <= mmax.  L then
+    // grows while the tile has room, absorbing needed qubits it passes.
+    int L = std::min(lmin, n);
+    int K = __builtin_popcountll(needed >> L);
+    while (L + K < mmax && L < n) {
+        ++L;
+        K = __builtin_popcountll(L < 64 ? needed >> L : 0);
+    }
+    sp->L = L;
+    sp->K = 0;
+    uint64_t hi = L < 64 ? (needed >> L) << L : 0;
+    while (hi) {
+        const int b = __builtin_ctzll(hi);
+        hi &= hi - 1;
+        sp->high[sp->K++] = b;
+    }
+}
+
+static int local_bit(const TileSpec &sp, int q) {
+    if (q < sp.L) return q;
+    for (int i = 0; i < sp.K; ++i)
+        if (sp.high[i] == q) return sp.L + i;
+    return -1;
+}
+
+static void encode_tile_gate(const TileSpec &sp, const Gate &g, TileGate *r) {
+    std::memset(r, 0, sizeof(*r));
+    r->b0 = local_bit(sp, g.t[0]);
+    r->b1 = g.k == 2 ? local_bit(sp, g.t[1]) : 0;
+    uint64_t c = g.ctrl;
+    while (c) {
+        const int b = __builtin_ctzll(c);
+        c &= c - 1;
+        const int lb = local_bit(sp, b);
+        if (lb >= 0) r->cin |= 1u << lb;
+        else r->cout |= 1ull << b;
+    }
+    if (g.k == 2) {
+        r->kind = TG_2Q;
+        std::memcpy(r->m, g.U, sizeof(double) * 32);
+    } else if (is_zero(g.U + 2) && is_zero(g.U + 4)) {
+        r->kind = TG_DIAG;
+        r->m[0] = g.U[0]; r->m[1] = g.U[1]; r->m[2] = g.U[6]; r->m[3] = g.U[7];
+    } else {
+        r->kind = TG_1Q;
+        std::memcpy(r->m, g.U, sizeof(double) * 8);
+    }
+}
+
+static void encode_pass(sv_state *h, const TileSpec &sp, const std::vector<const Gate *> &gs,
+                        size_t slot_offset) {
+    for (size_t i = 0; i < gs.size(); ++i) encode_tile_gate(sp, *gs[i], &h->h_gates[slot_offset + i]);
+}
+
+static int tile_single(sv_state *h, const Gate &g) {
+    int rc = ensure_gate_capacity(h, 1);
+    if (rc) return rc;
+    rc = stage_wait(h);
+    if (rc) return rc;
+    TileSpec sp{};
+    tile_layout(h->n, tile_max_qubits(h->dtype), std::min(h->n, 6), g.tmask(), &sp);
+    std::vector<const Gate *> one{&g};
+    encode_pass(h, sp, one, 0);
+    rc = upload_gates(h, 1);
+    if (rc) return rc;
+    SV_HIP(launch_tile(h->amps, h->n, h->dtype, sp, h->d_gates, 1, h->stream));
+    return SV_OK;
+}
+
+// Greedy, commutation-aware grouping: scan the unscheduled gates in order;
+// a gate joins the current pass if it does not touch a qubit of an earlier
+// gate left behind, and its targets fit in the tile (low block plus at most
+// kmax further qubits).  Gates left behind block their qubits for the rest
+// of the scan, so every pair of gates sharing a qubit keeps its order.
+static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, int lmin) {
+    std::vector<Pass> passes;
+    std::vector<char> done(gs.size(), 0);
+    size_t first = 0;
+    const uint64_t low = lmin >= 64 ? ~0ull : ((1ull << lmin) - 1ull);
+    const int kmax = std::max(0, mmax - lmin);
+    while (first < gs.size()) {
+        Pass p;
+        p.S = low;
+        uint64_t blocked = 0;
+        int used = 0;
+        for (size_t i = first; i < gs.size(); ++i) {
+            if (done[i]) continue;
+            const Gate &g = gs[i];
+            if (g.qmask() & blocked) {
+                blocked |= g.qmask();
+                continue;
+            }
+            const uint64_t need = g.tmask() & ~p.S;
+            const int nn = __builtin_popcountll(need);
+            if (used + nn <= kmax) {
+                p.S |= need;
+                used += nn;
+                p.gates.push_back((int)i);
+                done[i] = 1;
+            } else {
+                blocked |= g.qmask();
+            }
+        }
+        passes.push_back(std::move(p));
+        while (first < gs.size() && done[first]) ++first;
+    }
+    (void)n;
+    return passes;
+}
+
+// A single gate that the streamed kernels cannot take: a two-qubit gate with
+// a target inside a 16-byte complex64 vector.
+static bool needs_tile(const sv_state *h, const Gate &g) {
+    const int vb = vbits_of(h->dtype);
+    return g.k == 2 && (g.t[0] < vb || g.t[1] < vb);
+}
+
+static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
+    if (mode == SV_RUN_PER_GATE) {
+        for (const Gate &g : gs) {
+            const int rc = apply_one(h, g);
+            if (rc) return rc;
+        }
+        return SV_OK;
+    }
+    const int mmax = std::min(h->n, tile_max_qubits(h->dtype));
+    const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
+    std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin);
+    // stage every multi-gate pass's records, upload once, then launch in order
+    std::vector<char> tiled(passes.size(), 0);
+    size_t total = 0;
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const Pass &p = passes[pi];
+        tiled[pi] = p.gates.size() > 1 || (p.gates.size() == 1 && needs_tile(h, gs[p.gates[0]]));
+        if (tiled[pi]) total += p.gates.size();
+    }
+    if (total) {
+        int rc = ensure_gate_capacity(h, total);
+        if (rc) return rc;
+        rc = stage_wait(h);
+        if (rc) return rc;
+    }
+    std::vector<TileSpec> specs(passes.size());
+    std::vector<size_t> offs(passes.size(), 0);
+    size_t off = 0;
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const Pass &p = passes[pi];
+        if (!tiled[pi]) continue;
+        uint64_t needed = 0;
+        std::vector<const Gate *> ptrs;
+        for (int gi : p.gates) {
+            needed |= gs[gi].tmask();
+            ptrs.push_back(&gs[gi]);
+        }
+        tile_layout(h->n, mmax, lmin, needed, &specs[pi]);
+        encode_pass(h, specs[pi], ptrs, off);
+        offs[pi] = off;
+        off += p.gates.size();
+    }
+    if (total) {
+        const int rc = upload_gates(h, total);
+        if (rc) return rc;
+    }
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const Pass &p = passes[pi];
+        if (p.gates.empty()) continue;
+        if (!tiled[pi]) {
+            const int rc = apply_one(h, gs[p.gates[0]]);
+            if (rc) return rc;
+        } else {
+            SV_HIP(launch_tile(h->amps, h->n, h->dtype, specs[pi], h->d_gates + offs[pi],
+                               (int)p.gates.size(), h->stream));
+        }
+    }
+    return SV_OK;
+}
+
+} // namespace sv
+
+using namespace sv;
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char *sv_last_error(void) { return g_last_error.c_str(); }
+
+const char *sv_version(void) { return "svsim-gfx950 0.1"; }
+
+size_t sv_state_bytes(int n_qubits, int dtype) {
+    if (n_qubits < 1 || n_qubits > 40) return 0;
+    if (dtype != SV_C64 && dtype != SV_C128) return 0;
+    return (size_t(1) << n_qubits) * (dtype == SV_C64 ? 8 : 16);
+}
+
+int sv_alloc(int n_qubits, int dtype, void *dev_buf, void *hip_stream, sv_handle *out) {
+    if (!out) return fail(SV_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 40) return fail(SV_EINVAL, "n_qubits must be in [1, 40]");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    if (dev_buf && (reinterpret_cast<uintptr_t>(dev_buf) & 15u))
+        return fail(SV_EINVAL, "dev_buf must be 16-byte aligned");
+    const size_t bytes = sv_state_bytes(n_qubits, dtype);
+    sv_state *h = new sv_state();
+    h->n = n_qubits;
+    h->dtype = dtype;
+    h->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    if (!dev_buf) {
+        size_t free_b = 0, total_b = 0;
+        e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "hipMemGetInfo");
+        }
+        if (bytes + (64u << 20) > free_b) {
+            delete h;
+            return fail(SV_ENOMEM, "state of " + std::to_string(bytes) + " bytes exceeds free device memory");
+        }
+        e = hipMalloc(&h->amps, bytes);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(SV_ENOMEM, std::string("hipMalloc of the state failed: ") + hipGetErrorString(e));
+        }
+        h->owned = true;
+    } else {
+        h->amps = dev_buf;
+    }
+    int rc = SV_OK;
+    if ((e = hipMalloc((void **)&h->d_red, sizeof(double) * (kReduceBlocks + 1))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_result, sizeof(double) * 8, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->stage_done, hipEventDisableTiming)) != hipSuccess ||
+        (e = launch_init_basis(h->amps, h->n, h->dtype, 0, h->stream)) != hipSuccess) {
+        rc = hip_fail(e, "sv_alloc");
+        sv_free(h);
+        return rc;
+    }
+    *out = h;
+    return SV_OK;
+}
+
+int sv_free(sv_handle h) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    hipStreamSynchronize(h->stream);
+    if (h->owned && h->amps) hipFree(h->amps);
+    if (h->d_red) hipFree(h->d_red);
+    if (h->h_result) hipHostFree(h->h_result);
+    if (h->d_gates) hipFree(h->d_gates);
+    if (h->h_gates) hipHostFree(h->h_gates);
+    if (h->stage_done) hipEventDestroy(h->stage_done);
+    delete h;
+    return SV_OK;
+}
+
+int sv_set_basis(sv_handle h, uint64_t x) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (h->n < 64 && (x >> h->n) != 0) return fail(SV_EINVAL, "basis index >= 2^n");
+    SV_HIP(launch_init_basis(h->amps, h->n, h->dtype, x, h->stream));
+    return SV_OK;
+}
+
+int sv_set_stream(sv_handle h, void *hip_stream) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    int rc = stage_wait(h);
+    if (rc) return rc;
+    SV_HIP(hipStreamSynchronize(h->stream));
+    h->stream = (hipStream_t)hip_stream;
+    return SV_OK;
+}
+
+int sv_sync(sv_handle h) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    SV_HIP(hipStreamSynchronize(h->stream));
+    return SV_OK;
+}
+
+void *sv_data(sv_handle h) { return h ? h->amps : nullptr; }
+
+int sv_apply_gate(sv_handle h, int k, const int *targets, uint64_t ctrl_mask, const double *U) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    int rc = check_gate(h->n, k, targets, ctrl_mask, U);
+    if (rc) return rc;
+    Gate g;
+    g.k = k;
+    g.t[0] = targets[0];
+    g.t[1] = k == 2 ? targets[1] : -1;
+    g.ctrl = ctrl_mask;
+    std::memcpy(g.U, U, sizeof(double) * 2 * (1 << (2 * k)));
+    return apply_one(h, g);
+}
+
+int sv_run(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params, int mode) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(SV_EINVAL, "bad op list");
+    if (mode != SV_RUN_PER_GATE && mode != SV_RUN_TILED) return fail(SV_EINVAL, "unknown run mode");
+    std::vector<Gate> gs((size_t)n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+        const int rc = op_to_gate(h->n, ops[i], params, n_params, &gs[i]);
+        if (rc) return fail(rc, "op " + std::to_string(i) + ": " + g_last_error);
+    }
+    return run_gates(h, gs, mode);
+}
+
+int sv_probabilities(sv_handle h, void *dev_out, double *host_norm) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    SV_HIP(launch_probabilities(h->amps, h->n, h->dtype, dev_out, h->d_red, kReduceBlocks,
+                                h->d_red + kReduceBlocks, h->stream));
+    if (host_norm) {
+        SV_HIP(hipMemcpyAsync(h->h_result, h->d_red + kReduceBlocks, sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+        *host_norm = h->h_result[0];
+    }
+    return SV_OK;
+}
+
+int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const double *coeffs,
+                   double *host_out) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (n_terms < 1 || n_terms > kMaxTerms) return fail(SV_EINVAL, "n_terms must be in [1, 64]");
+    if (!z_masks || !coeffs || !host_out) return fail(SV_EINVAL, "NULL argument");
+    for (int j = 0; j < n_terms; ++j)
+        if (h->n < 64 && (z_masks[j] >> h->n) != 0) return fail(SV_EINVAL, "Z mask has bits >= n");
+    SV_HIP(launch_expectation(h->amps, h->n, h->dtype, n_terms, z_masks, coeffs, h->d_red,
+                              kReduceBlocks, h->d_red + kReduceBlocks, h->stream));
+    SV_HIP(hipMemcpyAsync(h->h_result, h->d_red + kReduceBlocks, sizeof(double),
+                          hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+    *host_out = h->h_result[0];
+    return SV_OK;
+}
+
+int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int prec) {
+    (void)h; (void)k; (void)qubits; (void)U; (void)prec;
+    return fail(SV_EUNSUPPORTED, "sv_apply_fused: not built yet");
+}
+
+int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int n_params,
+            int k_max, int max_blocks, int *block_k, int *block_qubits, double *block_mats,
+            int *block_gates, int *n_blocks) {
+    (void)n_qubits; (void)ops; (void)n_ops; (void)params; (void)n_params; (void)k_max;
+    (void)max_blocks; (void)block_k; (void)block_qubits; (void)block_mats; (void)block_gates;
+    (void)n_blocks;
+    return fail(SV_EUNSUPPORTED, "sv_fuse: not built yet");
+}
+
+int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
+                 int k_max, int prec, int *n_blocks_out) {
+    (void)h; (void)ops; (void)n_ops; (void)params; (void)n_params; (void)k_max; (void)prec;
+    (void)n_blocks_out;
+    return fail(SV_EUNSUPPORTED, "sv_run_fused: not built yet");
+}
+
+int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, const double *params,
+                    int n_params, int n_terms, const uint64_t *z_masks, const double *coeffs,
+                    double *host_loss, double *host_grad) {
+    (void)h; (void)lam; (void)ops; (void)n_ops; (void)params; (void)n_params; (void)n_terms;
+    (void)z_masks; (void)coeffs; (void)host_loss; (void)host_grad;
+    return fail(SV_EUNSUPPORTED, "sv_adjoint_grad: not built yet");
+}
+
+} // extern "C"

@@ -1,0 +1,237 @@
+"""GPU parity of the plain gate path against the FP64 oracle.
+
+Every case runs the HIP kernels through the C-ABI (via the Python binding)
+and the oracle on the same seeded input, and compares element by element.
+Sizes span one vector, several LDS tiles (tiles hold 2^12 / 2^13
+amplitudes) and ragged launch tails (pair counts below one workgroup's
+share)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+from helpers import assert_state_close, random_state
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1805_00988_amd as sv  # noqa: E402
+
+O.build(force=False)
+
+DTYPES = ["c128", "c64"]
+NP_DT = {"c128": np.complex128, "c64": np.complex64}
+
+
+def gpu_state(n, dtype, psi0=None):
+    st = sv.State(n, dtype)
+    if psi0 is not None:
+        st.amps.copy_(torch.from_numpy(psi0.astype(NP_DT[dtype])))
+    return st
+
+
+def oracle_input(psi0, dtype):
+    """The exact values the GPU starts from, widened to complex128."""
+    return psi0.astype(NP_DT[dtype]).astype(np.complex128)
+
+
+def run_both(n, dtype, gates, seed, mode):
+    psi0 = random_state(n, seed)
+    st = gpu_state(n, dtype, psi0)
+    st.run(gates, mode=mode)
+    got = st.numpy()
+    ref = O.run_gates(n, gates, oracle_input(psi0, dtype))
+    return got, ref
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 14])
+def test_one_qubit_gate_every_target(dtype, n):
+    rng = np.random.default_rng(100 + n)
+    for t in range(n):
+        U = C.random_unitary(2, rng)
+        g = C.Gate("U", (t,), (), 0.0, -1, U)
+        got, ref = run_both(n, dtype, [g], seed=t, mode=sv.SV_RUN_PER_GATE)
+        assert_state_close(got, ref, dtype, 1)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_controlled_gates(dtype):
+    n = 13
+    rng = np.random.default_rng(7)
+    cases = []
+    for t in range(n):
+        for nc in (1, 2, 3):
+            others = [q for q in range(n) if q != t]
+            ctrl = tuple(int(c) for c in rng.choice(others, size=nc, replace=False))
+            cases.append((t, ctrl))
+    cases += [(5, (0,)), (0, (1,)), (1, (0,)), (12, (0, 1)), (3, (0, 12, 7, 9, 11))]
+    for i, (t, ctrl) in enumerate(cases):
+        g = C.Gate("U", (t,), ctrl, 0.0, -1, C.random_unitary(2, rng))
+        got, ref = run_both(n, dtype, [g], seed=i, mode=sv.SV_RUN_PER_GATE)
+        assert_state_close(got, ref, dtype, 1)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_two_qubit_gates_all_pairs(dtype):
+    n = 6
+    rng = np.random.default_rng(8)
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            g = C.Gate("U", (a, b), (), 0.0, -1, C.random_unitary(4, rng))
+            got, ref = run_both(n, dtype, [g], seed=a * n + b, mode=sv.SV_RUN_PER_GATE)
+            assert_state_close(got, ref, dtype, 1)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_two_qubit_gates_controlled_large(dtype):
+    n = 15
+    circ = C.random_unitary_gates(n, 24, 2, seed=9, max_controls=2)
+    circ.gates += [C.Gate("U", (0, 14), (3,), 0.0, -1, C.random_unitary(4, np.random.default_rng(1))),
+                   C.Gate("U", (13, 0), (), 0.0, -1, C.random_unitary(4, np.random.default_rng(2)))]
+    for mode in (sv.SV_RUN_PER_GATE, sv.SV_RUN_TILED):
+        got, ref = run_both(n, dtype, circ.gates, seed=3, mode=mode)
+        assert_state_close(got, ref, dtype, len(circ.gates))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_diagonal_and_phase_gates(dtype):
+    n = 12
+    gates = []
+    rng = np.random.default_rng(4)
+    for t in range(n):
+        gates.append(C.Gate("U1", (t,), ((t + 3) % n,), float(rng.uniform(0, 6.28))))
+        gates.append(C.Gate(["Z", "S", "T"][t % 3], (t,)))
+        gates.append(C.Gate("RZ", (t,), (), float(rng.uniform(0, 6.28))))
+        gates.append(C.Gate("U1", (t,), (), float(rng.uniform(0, 6.28))))
+    gates.append(C.Gate("U1", (0,), (1, 2), 1.1))
+    gates.append(C.Gate("Z", (1,), (0,)))
+    for mode in (sv.SV_RUN_PER_GATE, sv.SV_RUN_TILED):
+        got, ref = run_both(n, dtype, gates, seed=5, mode=mode)
+        assert_state_close(got, ref, dtype, len(gates))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["per_gate", "tiled"])
+def test_config0_random_circuit(dtype, mode):
+    """Config 0 recipe (12 qubits from |0>, depth 20, 6 CNOTs per layer)."""
+    circ = C.config0(0)
+    st = sv.State(circ.n, dtype)
+    st.run(circ.gates, mode=sv.SV_RUN_TILED if mode == "tiled" else sv.SV_RUN_PER_GATE)
+    assert_state_close(st.numpy(), O.run(circ), dtype, len(circ))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [3, 9, 13, 16, 18])
+def test_random_circuits_tiled_vs_oracle(dtype, n):
+    circ = C.random_circuit(n, 12, seed=n, entangler="X")
+    st = sv.State(n, dtype)
+    st.run(circ.gates, mode=sv.SV_RUN_TILED)
+    assert_state_close(st.numpy(), O.run(circ), dtype, len(circ))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_cz_layers_tiled(dtype):
+    circ = C.config2(n=17, seed=1, depth=8)
+    st = sv.State(circ.n, dtype)
+    st.run(circ.gates, mode=sv.SV_RUN_TILED)
+    assert_state_close(st.numpy(), O.run(circ), dtype, len(circ))
+
+
+def bit_reverse(x, n):
+    return int(format(x, f"0{n}b")[::-1], 2)
+
+
+def qft_reference(n, x, ys):
+    r = bit_reverse(x, n)
+    ph = [(r * int(y)) % (1 << n) for y in ys]
+    return np.exp(1j * 2.0 * math.pi * np.array(ph, dtype=np.float64) / float(1 << n)) * 2.0 ** (-n / 2)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["per_gate", "tiled"])
+def test_qft_basis_state_closed_form(dtype, mode):
+    n = 15
+    x = C.random_basis(n, 11)
+    circ = C.qft_circuit(n, x)
+    st = sv.State(n, dtype).set_basis(x)
+    st.run(circ.gates, mode=sv.SV_RUN_TILED if mode == "tiled" else sv.SV_RUN_PER_GATE)
+    got = st.numpy()
+    ref = qft_reference(n, x, range(1 << n))
+    assert_state_close(got, ref, dtype, len(circ))
+    assert_state_close(got, O.run(circ), dtype, len(circ))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_bernstein_vazirani(dtype):
+    n, a = 14, 101
+    st = sv.State(n, dtype).run(C.bernstein_vazirani(n, a).gates)
+    p = torch.empty(1 << n, dtype=torch.float32 if dtype == "c64" else torch.float64, device="cuda")
+    total = st.probabilities(p)
+    p = p.cpu().numpy()
+    assert abs(p[a] - 1.0) < 1e-6 and abs(total - 1.0) < 1e-6
+    assert int(np.argmax(p)) == a
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 5, 12, 17])
+def test_probabilities_match_oracle(dtype, n):
+    circ = C.random_circuit(n, 6, seed=20 + n, entangler="X")
+    st = sv.State(n, dtype).run(circ.gates)
+    p = torch.empty(1 << n, dtype=torch.float32 if dtype == "c64" else torch.float64, device="cuda")
+    total = st.probabilities(p)
+    amps = st.numpy().astype(np.complex128)
+    # reference from the GPU's own amplitudes (isolates the reduction) and
+    # from the oracle state (end to end)
+    p_ref, t_ref = O.probabilities(amps, n)
+    got = p.cpu().numpy().astype(np.float64)
+    if dtype == "c128":
+        np.testing.assert_allclose(got, p_ref, rtol=0, atol=1e-15)
+        assert abs(total - t_ref) < 1e-13
+    else:
+        np.testing.assert_allclose(got, p_ref, rtol=4 * 2.0 ** -24, atol=1e-30)
+        assert abs(total - t_ref) < 1e-12
+    p_orc, _ = O.probabilities(O.run(circ), n)
+    np.testing.assert_allclose(got, p_orc, rtol=0, atol=1e-12 if dtype == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [2, 10, 16])
+def test_expectation_match_oracle(dtype, n):
+    circ = C.random_circuit(n, 5, seed=40 + n, entangler="X")
+    st = sv.State(n, dtype).run(circ.gates)
+    rng = np.random.default_rng(n)
+    masks = [int(m) for m in rng.integers(0, 1 << n, size=9)] + [1, (1 << n) - 1, 0]
+    coeffs = [float(c) for c in rng.standard_normal(len(masks))]
+    got = st.expectation(masks, coeffs)
+    amps = st.numpy().astype(np.complex128)
+    ref_same_input = O.expectation_z(amps, n, masks, coeffs)
+    tol = 1e-12 if dtype == "c128" else 1e-10
+    assert abs(got - ref_same_input) <= tol * max(1.0, sum(abs(c) for c in coeffs))
+    ref = O.expectation_z(O.run(circ), n, masks, coeffs)
+    assert abs(got - ref) <= (1e-11 if dtype == "c128" else 1e-4) * sum(abs(c) for c in coeffs)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_invalid_arguments_leave_state_unchanged(dtype):
+    n = 8
+    psi0 = random_state(n, 1)
+    st = gpu_state(n, dtype, psi0)
+    before = st.numpy().copy()
+    with pytest.raises(sv.SVError):
+        st.apply(np.eye(2), [n])            # target out of range
+    with pytest.raises(sv.SVError):
+        st.apply(np.eye(2), [3], [3])       # control equals target
+    with pytest.raises(sv.SVError):
+        st.apply(np.eye(4), [2, 2])         # duplicate targets
+    with pytest.raises(sv.SVError):
+        st.apply(np.eye(2), [1], [n + 1])   # control out of range
+    with pytest.raises(sv.SVError):
+        st.set_basis(1 << n)
+    np.testing.assert_array_equal(st.numpy(), before)
