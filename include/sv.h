@@ -190,6 +190,25 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops,
                     const double *params, int n_params, int n_terms, const uint64_t *z_masks,
                     const double *coeffs, double *host_loss, double *host_grad);
 
+/* Per-launch timing of a handle's kernels, for measurement: with timing on,
+ * every kernel launch of the handle is bracketed by two HIP events recorded
+ * on the handle's stream.  sv_timing(h, 1) starts (and clears) a record,
+ * sv_timing(h, 0) stops recording; both wait for the stream first.
+ * sv_timing_read waits for the stream and writes one entry per kernel kind
+ * that ran since the record was cleared: launches, summed event time and the
+ * summed algorithmic HBM bytes of those launches (every amplitude a launch
+ * must read and write once: 2 * bytes-per-amplitude * amplitudes touched for
+ * a gate or tile pass).  *n_out receives the number of kinds; SV_EINVAL if it
+ * exceeds cap.  Reading clears the record. */
+typedef struct sv_kernel_stat {
+    char name[24];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} sv_kernel_stat;
+int sv_timing(sv_handle h, int enable);
+int sv_timing_read(sv_handle h, sv_kernel_stat *out, int cap, int *n_out);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *sv_last_error(void);
 

@@ -22,8 +22,8 @@ GATE_KINDS = {"H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6,
 
 EXPORTED = ("sv_state_bytes", "sv_alloc", "sv_free", "sv_set_basis", "sv_set_stream", "sv_sync",
             "sv_data", "sv_apply_gate", "sv_apply_fused", "sv_probabilities", "sv_expectation",
-            "sv_run", "sv_fuse", "sv_run_fused", "sv_adjoint_grad", "sv_last_error",
-            "sv_version")
+            "sv_run", "sv_fuse", "sv_run_fused", "sv_adjoint_grad", "sv_timing",
+            "sv_timing_read", "sv_last_error", "sv_version")
 
 
 class sv_op(ctypes.Structure):
@@ -31,6 +31,11 @@ class sv_op(ctypes.Structure):
                 ("targets", ctypes.c_int32 * 2), ("ctrl_mask", ctypes.c_uint64),
                 ("param_index", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("theta", ctypes.c_double), ("matrix", ctypes.c_double * 32)]
+
+
+class sv_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class SVError(RuntimeError):
@@ -66,6 +71,8 @@ _PROTOS = {
     "sv_fuse": (_I, [_I, _OPP, _I, _DP, _I, _I, _I, _IP, _IP, _DP, _IP, _IP]),
     "sv_run_fused": (_I, [_P, _OPP, _I, _DP, _I, _I, _I, _IP]),
     "sv_adjoint_grad": (_I, [_P, _P, _OPP, _I, _DP, _I, _I, _U64P, _DP, _DP, _DP]),
+    "sv_timing": (_I, [_P, _I]),
+    "sv_timing_read": (_I, [_P, ctypes.POINTER(sv_kernel_stat), _I, _IP]),
     "sv_last_error": (ctypes.c_char_p, []),
     "sv_version": (ctypes.c_char_p, []),
 }

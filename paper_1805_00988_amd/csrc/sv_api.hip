@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -23,6 +24,16 @@ struct sv_state {
     sv::TileGate *h_gates = nullptr;  // pinned staging for d_gates
     hipEvent_t stage_done = nullptr;  // last copy out of h_gates
     bool stage_pending = false;
+    // per-launch timing (sv_timing): event pairs around each kernel launch
+    struct Rec {
+        int kid;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
 };
 
 namespace sv {
@@ -45,6 +56,45 @@ static int hip_fail(hipError_t e, const char *where) {
         hipError_t e_ = (call);                                                                    \
         if (e_ != hipSuccess) return hip_fail(e_, #call);                                          \
     } while (0)
+
+// ----------------------------------------------------------- launch timing
+enum KernelId { K_INIT, K_GATE1, K_GATE2, K_SCALE, K_TILE, K_PROBS, K_EXPECT, K_FUSED, K_ADJOINT,
+                K_COUNT };
+static const char *kKernelNames[K_COUNT] = {"init_basis", "gate1_stream", "gate2_stream",
+                                            "scale_subspace", "tile_pass", "probabilities",
+                                            "expectation", "fused_block", "adjoint_step"};
+
+static hipEvent_t take_event(sv_state *h) {
+    if (h->pool_used == h->pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->pool.push_back(e);
+    }
+    return h->pool[h->pool_used++];
+}
+
+// Brackets one kernel launch with events on the handle's stream when timing
+// is on; 'bytes' is the algorithmic HBM traffic of the launch.
+struct Timed {
+    sv_state *h;
+    int kid;
+    double bytes;
+    hipEvent_t a = nullptr;
+    Timed(sv_state *h_, int kid_, double bytes_) : h(h_), kid(kid_), bytes(bytes_) {
+        if (h->timing && (a = take_event(h)) != nullptr) (void)hipEventRecord(a, h->stream);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(h);
+        if (!b) return;
+        (void)hipEventRecord(b, h->stream);
+        h->recs.push_back({kid, bytes, a, b});
+    }
+};
+
+static double state_bytes(const sv_state *h) {
+    return (double)(1ull << h->n) * (h->dtype == SV_C64 ? 8.0 : 16.0);
+}
 
 // ------------------------------------------------------------ gate table
 // H X Y Z S T per the gate table of Sec. 1.3.2; rotations exp(-i theta P/2);
@@ -175,16 +225,19 @@ static int apply_one(sv_state *h, const Gate &g) {
         if (is_zero(U + 2) && is_zero(U + 4)) {
             if (is_one(U) && is_one(U + 6)) return SV_OK; // identity
             if (is_one(U)) {
-                SV_HIP(launch_scale(h->amps, h->n, h->dtype, g.ctrl | (1ull << g.t[0]), U + 6,
-                                    h->stream));
+                const uint64_t mask = g.ctrl | (1ull << g.t[0]);
+                Timed tm(h, K_SCALE, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(mask)));
+                SV_HIP(launch_scale(h->amps, h->n, h->dtype, mask, U + 6, h->stream));
                 return SV_OK;
             }
         }
+        Timed tm(h, K_GATE1, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(g.ctrl)));
         SV_HIP(launch_gate1(h->amps, h->n, h->dtype, g.t[0], g.ctrl, g.U, h->stream));
         return SV_OK;
     }
     const int vb = vbits_of(h->dtype);
     if (g.t[0] >= vb && g.t[1] >= vb) {
+        Timed tm(h, K_GATE2, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(g.ctrl)));
         SV_HIP(launch_gate2(h->amps, h->n, h->dtype, g.t[0], g.t[1], g.ctrl, g.U, h->stream));
         return SV_OK;
     }
@@ -264,6 +317,7 @@ static int tile_single(sv_state *h, const Gate &g) {
     encode_pass(h, sp, one, 0);
     rc = upload_gates(h, 1);
     if (rc) return rc;
+    Timed tm(h, K_TILE, 2.0 * state_bytes(h));
     SV_HIP(launch_tile(h->amps, h->n, h->dtype, sp, h->d_gates, 1, h->stream));
     return SV_OK;
 }
@@ -369,6 +423,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
             const int rc = apply_one(h, gs[p.gates[0]]);
             if (rc) return rc;
         } else {
+            Timed tm(h, K_TILE, 2.0 * state_bytes(h));
             SV_HIP(launch_tile(h->amps, h->n, h->dtype, specs[pi], h->d_gates + offs[pi],
                                (int)p.gates.size(), h->stream));
         }
@@ -452,6 +507,7 @@ int sv_free(sv_handle h) {
     if (h->d_gates) hipFree(h->d_gates);
     if (h->h_gates) hipHostFree(h->h_gates);
     if (h->stage_done) hipEventDestroy(h->stage_done);
+    for (hipEvent_t e : h->pool) hipEventDestroy(e);
     delete h;
     return SV_OK;
 }
@@ -459,6 +515,7 @@ int sv_free(sv_handle h) {
 int sv_set_basis(sv_handle h, uint64_t x) {
     if (!h) return fail(SV_EINVAL, "NULL handle");
     if (h->n < 64 && (x >> h->n) != 0) return fail(SV_EINVAL, "basis index >= 2^n");
+    Timed tm(h, K_INIT, state_bytes(h));
     SV_HIP(launch_init_basis(h->amps, h->n, h->dtype, x, h->stream));
     return SV_OK;
 }
@@ -507,8 +564,11 @@ int sv_run(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n
 
 int sv_probabilities(sv_handle h, void *dev_out, double *host_norm) {
     if (!h) return fail(SV_EINVAL, "NULL handle");
-    SV_HIP(launch_probabilities(h->amps, h->n, h->dtype, dev_out, h->d_red, kReduceBlocks,
-                                h->d_red + kReduceBlocks, h->stream));
+    {
+        Timed tm(h, K_PROBS, state_bytes(h) * (dev_out ? 1.5 : 1.0));
+        SV_HIP(launch_probabilities(h->amps, h->n, h->dtype, dev_out, h->d_red, kReduceBlocks,
+                                    h->d_red + kReduceBlocks, h->stream));
+    }
     if (host_norm) {
         SV_HIP(hipMemcpyAsync(h->h_result, h->d_red + kReduceBlocks, sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
@@ -525,13 +585,52 @@ int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const doub
     if (!z_masks || !coeffs || !host_out) return fail(SV_EINVAL, "NULL argument");
     for (int j = 0; j < n_terms; ++j)
         if (h->n < 64 && (z_masks[j] >> h->n) != 0) return fail(SV_EINVAL, "Z mask has bits >= n");
-    SV_HIP(launch_expectation(h->amps, h->n, h->dtype, n_terms, z_masks, coeffs, h->d_red,
-                              kReduceBlocks, h->d_red + kReduceBlocks, h->stream));
+    {
+        Timed tm(h, K_EXPECT, state_bytes(h));
+        SV_HIP(launch_expectation(h->amps, h->n, h->dtype, n_terms, z_masks, coeffs, h->d_red,
+                                  kReduceBlocks, h->d_red + kReduceBlocks, h->stream));
+    }
     SV_HIP(hipMemcpyAsync(h->h_result, h->d_red + kReduceBlocks, sizeof(double),
                           hipMemcpyDeviceToHost, h->stream));
     SV_HIP(hipStreamSynchronize(h->stream));
     *host_out = h->h_result[0];
     return SV_OK;
+}
+
+int sv_timing(sv_handle h, int enable) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    SV_HIP(hipStreamSynchronize(h->stream));
+    h->recs.clear();
+    h->pool_used = 0;
+    h->timing = enable != 0;
+    return SV_OK;
+}
+
+int sv_timing_read(sv_handle h, sv_kernel_stat *out, int cap, int *n_out) {
+    if (!h || !n_out || (cap > 0 && !out)) return fail(SV_EINVAL, "NULL argument");
+    SV_HIP(hipStreamSynchronize(h->stream));
+    sv_kernel_stat acc[K_COUNT];
+    std::memset(acc, 0, sizeof(acc));
+    for (const auto &r : h->recs) {
+        float ms = 0.0f;
+        SV_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        acc[r.kid].launches += 1;
+        acc[r.kid].total_ms += ms;
+        acc[r.kid].bytes += r.bytes;
+    }
+    int n = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (acc[k].launches == 0) continue;
+        if (n < cap) {
+            out[n] = acc[k];
+            std::snprintf(out[n].name, sizeof(out[n].name), "%s", kKernelNames[k]);
+        }
+        ++n;
+    }
+    *n_out = n;
+    h->recs.clear();
+    h->pool_used = 0;
+    return n > cap ? fail(SV_EINVAL, "cap too small") : SV_OK;
 }
 
 int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int prec) {
