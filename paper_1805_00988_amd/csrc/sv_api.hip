@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -19,10 +20,13 @@ struct sv_state {
     int device = 0;
     double *d_red = nullptr;          // kReduceBlocks partials + 1 total
     double *h_result = nullptr;       // pinned, 8 doubles
-    sv::TileGate *d_gates = nullptr;  // tile-pass gate records
-    size_t gates_cap = 0;
-    sv::TileGate *h_gates = nullptr;  // pinned staging for d_gates
-    hipEvent_t stage_done = nullptr;  // last copy out of h_gates
+    // staging arena: per-call records (tile-pass gates, block matrices,
+    // MFMA operand fragments) written to pinned host memory and copied once
+    // per call to the device arena on the handle's stream
+    char *d_arena = nullptr;
+    char *h_arena = nullptr;
+    size_t arena_cap = 0;
+    hipEvent_t stage_done = nullptr;  // last copy out of h_arena
     bool stage_pending = false;
     // per-launch timing (sv_timing): event pairs around each kernel launch
     struct Rec {
@@ -174,34 +178,36 @@ static int op_to_gate(int n, const sv_op &op, const double *params, int n_params
 }
 
 // ---------------------------------------------------------------- buffers
-static int ensure_gate_capacity(sv_state *h, size_t count) {
-    if (count <= h->gates_cap) return SV_OK;
-    size_t cap = std::max<size_t>(64, h->gates_cap);
-    while (cap < count) cap *= 2;
+static int ensure_arena(sv_state *h, size_t bytes) {
+    if (bytes <= h->arena_cap) return SV_OK;
+    size_t cap = std::max<size_t>(1 << 16, h->arena_cap);
+    while (cap < bytes) cap *= 2;
     if (h->stage_pending) SV_HIP(hipEventSynchronize(h->stage_done));
-    // the old device buffer may still be read by queued kernels: drain first
+    // the old device arena may still be read by queued kernels: drain first
     SV_HIP(hipStreamSynchronize(h->stream));
     h->stage_pending = false;
-    if (h->d_gates) SV_HIP(hipFree(h->d_gates));
-    if (h->h_gates) SV_HIP(hipHostFree(h->h_gates));
-    h->d_gates = nullptr;
-    h->h_gates = nullptr;
-    h->gates_cap = 0;
-    SV_HIP(hipMalloc((void **)&h->d_gates, cap * sizeof(TileGate)));
-    SV_HIP(hipHostMalloc((void **)&h->h_gates, cap * sizeof(TileGate), hipHostMallocDefault));
-    h->gates_cap = cap;
+    if (h->d_arena) SV_HIP(hipFree(h->d_arena));
+    if (h->h_arena) SV_HIP(hipHostFree(h->h_arena));
+    h->d_arena = nullptr;
+    h->h_arena = nullptr;
+    h->arena_cap = 0;
+    SV_HIP(hipMalloc((void **)&h->d_arena, cap));
+    SV_HIP(hipHostMalloc((void **)&h->h_arena, cap, hipHostMallocDefault));
+    h->arena_cap = cap;
     return SV_OK;
 }
 
-// Copy staged gate records to the device on the handle's stream.  Kernels
-// queued earlier that read d_gates finish before the copy (stream order).
-static int upload_gates(sv_state *h, size_t count) {
-    SV_HIP(hipMemcpyAsync(h->d_gates, h->h_gates, count * sizeof(TileGate), hipMemcpyHostToDevice,
-                          h->stream));
+// Copy the staged bytes to the device arena on the handle's stream.  Kernels
+// queued earlier that read the arena finish before the copy (stream order).
+static int upload_arena(sv_state *h, size_t bytes) {
+    SV_HIP(hipMemcpyAsync(h->d_arena, h->h_arena, bytes, hipMemcpyHostToDevice, h->stream));
     SV_HIP(hipEventRecord(h->stage_done, h->stream));
     h->stage_pending = true;
     return SV_OK;
 }
+
+static TileGate *h_gates(sv_state *h) { return reinterpret_cast<TileGate *>(h->h_arena); }
+static TileGate *d_gates(sv_state *h) { return reinterpret_cast<TileGate *>(h->d_arena); }
 
 static int stage_wait(sv_state *h) {
     if (h->stage_pending) SV_HIP(hipEventSynchronize(h->stage_done));
@@ -303,11 +309,11 @@ static void encode_tile_gate(const TileSpec &sp, const Gate &g, TileGate *r) {
 
 static void encode_pass(sv_state *h, const TileSpec &sp, const std::vector<const Gate *> &gs,
                         size_t slot_offset) {
-    for (size_t i = 0; i < gs.size(); ++i) encode_tile_gate(sp, *gs[i], &h->h_gates[slot_offset + i]);
+    for (size_t i = 0; i < gs.size(); ++i) encode_tile_gate(sp, *gs[i], &h_gates(h)[slot_offset + i]);
 }
 
 static int tile_single(sv_state *h, const Gate &g) {
-    int rc = ensure_gate_capacity(h, 1);
+    int rc = ensure_arena(h, sizeof(TileGate));
     if (rc) return rc;
     rc = stage_wait(h);
     if (rc) return rc;
@@ -315,10 +321,10 @@ static int tile_single(sv_state *h, const Gate &g) {
     tile_layout(h->n, tile_max_qubits(h->dtype), std::min(h->n, 6), g.tmask(), &sp);
     std::vector<const Gate *> one{&g};
     encode_pass(h, sp, one, 0);
-    rc = upload_gates(h, 1);
+    rc = upload_arena(h, sizeof(TileGate));
     if (rc) return rc;
     Timed tm(h, K_TILE, 2.0 * state_bytes(h));
-    SV_HIP(launch_tile(h->amps, h->n, h->dtype, sp, h->d_gates, 1, h->stream));
+    SV_HIP(launch_tile(h->amps, h->n, h->dtype, sp, d_gates(h), 1, h->stream));
     return SV_OK;
 }
 
@@ -390,7 +396,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         if (tiled[pi]) total += p.gates.size();
     }
     if (total) {
-        int rc = ensure_gate_capacity(h, total);
+        int rc = ensure_arena(h, total * sizeof(TileGate));
         if (rc) return rc;
         rc = stage_wait(h);
         if (rc) return rc;
@@ -413,7 +419,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         off += p.gates.size();
     }
     if (total) {
-        const int rc = upload_gates(h, total);
+        const int rc = upload_arena(h, total * sizeof(TileGate));
         if (rc) return rc;
     }
     for (size_t pi = 0; pi < passes.size(); ++pi) {
@@ -424,9 +430,241 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
             if (rc) return rc;
         } else {
             Timed tm(h, K_TILE, 2.0 * state_bytes(h));
-            SV_HIP(launch_tile(h->amps, h->n, h->dtype, specs[pi], h->d_gates + offs[pi],
+            SV_HIP(launch_tile(h->amps, h->n, h->dtype, specs[pi], d_gates(h) + offs[pi],
                                (int)p.gates.size(), h->stream));
         }
+    }
+    return SV_OK;
+}
+
+
+// ================================================================ fusion
+// A dense block: qubits ascending (bit j of the matrix index <-> q[j]) and its
+// 2^k x 2^k matrix, row-major, FP64.
+struct Block {
+    int k = 0;
+    int q[5] = {0, 0, 0, 0, 0};
+    std::vector<std::complex<double>> M;
+    int n_gates = 0;
+};
+
+// Left-multiply the block matrix by gate g embedded in the block's qubits:
+// each column of M is a 2^k-amplitude vector and g acts on it as on a state.
+static void absorb(Block &b, const Gate &g) {
+    const int D = 1 << b.k;
+    auto local = [&](int q) {
+        for (int j = 0; j < b.k; ++j)
+            if (b.q[j] == q) return j;
+        return -1;
+    };
+    uint32_t lctrl = 0;
+    for (uint64_t c = g.ctrl; c; c &= c - 1) lctrl |= 1u << local(__builtin_ctzll(c));
+    std::complex<double> G[16];
+    for (int i = 0; i < (1 << (2 * g.k)); ++i) G[i] = {g.U[2 * i], g.U[2 * i + 1]};
+    if (g.k == 1) {
+        const int t = local(g.t[0]);
+        for (int a = 0; a < D; ++a) {
+            if ((a >> t) & 1) continue;
+            if (((uint32_t)a & lctrl) != lctrl) continue;
+            const int c = a | (1 << t);
+            for (int col = 0; col < D; ++col) {
+                const std::complex<double> x0 = b.M[(size_t)a * D + col], x1 = b.M[(size_t)c * D + col];
+                b.M[(size_t)a * D + col] = G[0] * x0 + G[1] * x1;
+                b.M[(size_t)c * D + col] = G[2] * x0 + G[3] * x1;
+            }
+        }
+    } else {
+        const int t0 = local(g.t[0]), t1 = local(g.t[1]);
+        for (int a = 0; a < D; ++a) {
+            if (((a >> t0) & 1) || ((a >> t1) & 1)) continue;
+            if (((uint32_t)a & lctrl) != lctrl) continue;
+            const int idx[4] = {a, a | (1 << t0), a | (1 << t1), a | (1 << t0) | (1 << t1)};
+            for (int col = 0; col < D; ++col) {
+                std::complex<double> x[4], y[4];
+                for (int r = 0; r < 4; ++r) x[r] = b.M[(size_t)idx[r] * D + col];
+                for (int r = 0; r < 4; ++r) {
+                    y[r] = 0;
+                    for (int c = 0; c < 4; ++c) y[r] += G[4 * r + c] * x[c];
+                }
+                for (int r = 0; r < 4; ++r) b.M[(size_t)idx[r] * D + col] = y[r];
+            }
+        }
+    }
+    b.n_gates += 1;
+}
+
+// Commutation-aware greedy fusion: scan the unplaced gates in order; a gate
+// joins the open block if it touches no qubit of a gate left behind earlier
+// in the scan and the block's qubit set (targets and controls) stays within
+// k_max; otherwise its qubits are blocked for the rest of the scan.  Gates
+// that share a qubit therefore keep their relative order.
+static std::vector<Block> fuse(const std::vector<Gate> &gs, int k_max) {
+    std::vector<Block> out;
+    std::vector<char> done(gs.size(), 0);
+    size_t first = 0;
+    while (first < gs.size()) {
+        uint64_t set = 0, blocked = 0;
+        std::vector<int> members;
+        for (size_t i = first; i < gs.size(); ++i) {
+            if (done[i]) continue;
+            const uint64_t gq = gs[i].qmask();
+            if (gq & blocked) {
+                blocked |= gq;
+                continue;
+            }
+            if (__builtin_popcountll(set | gq) <= k_max) {
+                set |= gq;
+                members.push_back((int)i);
+                done[i] = 1;
+            } else {
+                blocked |= gq;
+            }
+        }
+        Block b;
+        for (uint64_t m = set; m; m &= m - 1) b.q[b.k++] = __builtin_ctzll(m);
+        const int D = 1 << b.k;
+        b.M.assign((size_t)D * D, 0.0);
+        for (int i = 0; i < D; ++i) b.M[(size_t)i * D + i] = 1.0;
+        for (int gi : members) absorb(b, gs[gi]);
+        out.push_back(std::move(b));
+        while (first < gs.size() && done[first]) ++first;
+    }
+    return out;
+}
+
+// ---------------------------------------------- MFMA operand fragments
+static uint16_t bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u); // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+static float bf16_value(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// B operand of the two real GEMMs (K_total = 2D rows, D columns):
+//   part 0 (Re Y): rows [0,D) Re U^T, rows [D,2D) -Im U^T
+//   part 1 (Im Y): rows [0,D) Im U^T, rows [D,2D)  Re U^T
+static float bpart(const std::complex<double> *U, int D, int part, int krow, int col) {
+    const bool top = krow < D;
+    const std::complex<double> u = U[(size_t)col * D + (top ? krow : krow - D)];
+    if (part == 0) return (float)(top ? u.real() : -u.imag());
+    return (float)(top ? u.imag() : u.real());
+}
+
+// Bytes of the fragment buffer for (k, prec).
+static size_t frag_bytes(int k, int prec) {
+    if (prec == SV_PREC_FP32) return (size_t)2 * (k == 5 ? 32 : 8) * 64 * 4;
+    return (size_t)2 * (k == 5 ? 4 : 1) * 2 * 64 * 16;
+}
+
+// Lay out U in the per-lane order the MFMA kernel loads (see k_fused.hip).
+static void make_fragments(const std::complex<double> *U, int k, int prec, char *out) {
+    const int D = 1 << k;
+    if (prec == SV_PREC_FP32) {
+        float *f = reinterpret_cast<float *>(out);
+        const int rows = k == 5 ? 32 : 16, per = k == 5 ? 2 : 4, KS = 2 * D / per;
+        for (int p = 0; p < 2; ++p)
+            for (int st = 0; st < KS; ++st)
+                for (int lane = 0; lane < 64; ++lane)
+                    f[(p * KS + st) * 64 + lane] =
+                        bpart(U, D, p, per * st + lane / rows, lane % rows);
+    } else {
+        uint16_t *f = reinterpret_cast<uint16_t *>(out);
+        const int rows = k == 5 ? 32 : 16, KS = k == 5 ? 4 : 1;
+        for (int p = 0; p < 2; ++p)
+            for (int st = 0; st < KS; ++st)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int e = 0; e < 8; ++e) {
+                        const int krow = k == 5 ? 16 * st + 8 * (lane / rows) + e : 8 * (lane / rows) + e;
+                        const float x = bpart(U, D, p, krow, lane % rows);
+                        const uint16_t hi = bf16_bits(x);
+                        const uint16_t lo = bf16_bits(x - bf16_value(hi));
+                        f[(((p * KS + st) * 2 + 0) * 64 + lane) * 8 + e] = hi;
+                        f[(((p * KS + st) * 2 + 1) * 64 + lane) * 8 + e] = lo;
+                    }
+    }
+}
+
+// Whether a k-qubit MFMA block can run on this state (whole wave-tiles).
+static bool mfma_ok(const sv_state *h, int k, int prec) {
+    if (prec == SV_PREC_NATIVE || h->dtype != SV_C64 || (k != 4 && k != 5)) return false;
+    const int m = std::min(h->n, fused_tile_qubits(h->dtype));
+    const int rows = k == 5 ? 32 : 16;
+    return m >= k && ((1u << m) >> k) % rows == 0;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes a block needs in the arena (matrix in the state's precision, or the
+// MFMA fragments).
+static size_t block_stage_bytes(const sv_state *h, int k, bool mfma, int prec) {
+    if (mfma) return align256(frag_bytes(k, prec));
+    const size_t el = h->dtype == SV_C64 ? 8 : 16;
+    return align256(((size_t)1 << (2 * k)) * el);
+}
+
+static void stage_block(sv_state *h, const std::complex<double> *U, int k, bool mfma, int prec,
+                        size_t off) {
+    char *dst = h->h_arena + off;
+    if (mfma) {
+        make_fragments(U, k, prec, dst);
+        return;
+    }
+    const int n = 1 << (2 * k);
+    if (h->dtype == SV_C64) {
+        float *f = reinterpret_cast<float *>(dst);
+        for (int i = 0; i < n; ++i) {
+            f[2 * i] = (float)U[i].real();
+            f[2 * i + 1] = (float)U[i].imag();
+        }
+    } else {
+        double *d = reinterpret_cast<double *>(dst);
+        for (int i = 0; i < n; ++i) {
+            d[2 * i] = U[i].real();
+            d[2 * i + 1] = U[i].imag();
+        }
+    }
+}
+
+static int launch_block(sv_state *h, int k, const int *qubits, bool mfma, int prec, size_t off) {
+    uint64_t needed = 0;
+    for (int j = 0; j < k; ++j) needed |= 1ull << qubits[j];
+    TileSpec sp{};
+    const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
+    tile_layout(h->n, mmax, std::min(h->n, h->dtype == SV_C64 ? 7 : 6), needed, &sp);
+    Timed tm(h, K_FUSED, 2.0 * state_bytes(h));
+    SV_HIP(launch_dense(h->amps, h->n, h->dtype, sp, k, qubits, h->d_arena + off,
+                        mfma ? prec : SV_PREC_NATIVE, h->stream));
+    return SV_OK;
+}
+
+// Gate of a 1- or 2-qubit block, for the streamed kernels.
+static Gate block_gate(const Block &b) {
+    Gate g{};
+    g.k = b.k;
+    g.t[0] = b.q[0];
+    g.t[1] = b.k == 2 ? b.q[1] : -1;
+    g.ctrl = 0;
+    for (int i = 0; i < (1 << (2 * b.k)); ++i) {
+        g.U[2 * i] = b.M[i].real();
+        g.U[2 * i + 1] = b.M[i].imag();
+    }
+    return g;
+}
+
+static int parse_ops(const sv_state *h, int n, const sv_op *ops, int n_ops, const double *params,
+                     int n_params, std::vector<Gate> &gs) {
+    (void)h;
+    if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(SV_EINVAL, "bad op list");
+    gs.resize((size_t)n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+        const int rc = op_to_gate(n, ops[i], params, n_params, &gs[i]);
+        if (rc) return fail(rc, "op " + std::to_string(i) + ": " + g_last_error);
     }
     return SV_OK;
 }
@@ -504,8 +742,8 @@ int sv_free(sv_handle h) {
     if (h->owned && h->amps) hipFree(h->amps);
     if (h->d_red) hipFree(h->d_red);
     if (h->h_result) hipHostFree(h->h_result);
-    if (h->d_gates) hipFree(h->d_gates);
-    if (h->h_gates) hipHostFree(h->h_gates);
+    if (h->d_arena) hipFree(h->d_arena);
+    if (h->h_arena) hipHostFree(h->h_arena);
     if (h->stage_done) hipEventDestroy(h->stage_done);
     for (hipEvent_t e : h->pool) hipEventDestroy(e);
     delete h;
@@ -634,24 +872,111 @@ int sv_timing_read(sv_handle h, sv_kernel_stat *out, int cap, int *n_out) {
 }
 
 int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int prec) {
-    (void)h; (void)k; (void)qubits; (void)U; (void)prec;
-    return fail(SV_EUNSUPPORTED, "sv_apply_fused: not built yet");
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (!qubits || !U) return fail(SV_EINVAL, "NULL qubits or matrix");
+    if (k < 1 || k > 5) return fail(SV_EINVAL, "k must be in [1, 5]");
+    if (k > h->n) return fail(SV_EINVAL, "k exceeds the register size");
+    if (prec != SV_PREC_NATIVE && prec != SV_PREC_FP32 && prec != SV_PREC_SPLIT_BF16)
+        return fail(SV_EINVAL, "unknown precision");
+    uint64_t seen = 0;
+    for (int j = 0; j < k; ++j) {
+        if (qubits[j] < 0 || qubits[j] >= h->n) return fail(SV_EINVAL, "qubit outside [0, n)");
+        if (seen & (1ull << qubits[j])) return fail(SV_EINVAL, "duplicate qubits");
+        seen |= 1ull << qubits[j];
+    }
+    const int D = 1 << k;
+    for (int i = 0; i < 2 * D * D; ++i)
+        if (!std::isfinite(U[i])) return fail(SV_EINVAL, "matrix entry is not finite");
+    if (prec != SV_PREC_NATIVE && (h->dtype != SV_C64 || k < 4))
+        return fail(SV_EUNSUPPORTED, "matrix-core blocks need a complex64 state and k >= 4");
+    std::vector<std::complex<double>> M((size_t)D * D);
+    for (int i = 0; i < D * D; ++i) M[i] = {U[2 * i], U[2 * i + 1]};
+    const bool mfma = mfma_ok(h, k, prec);
+    const size_t bytes = block_stage_bytes(h, k, mfma, prec);
+    int rc = ensure_arena(h, bytes);
+    if (rc) return rc;
+    if ((rc = stage_wait(h))) return rc;
+    stage_block(h, M.data(), k, mfma, prec, 0);
+    if ((rc = upload_arena(h, bytes))) return rc;
+    return launch_block(h, k, qubits, mfma, prec, 0);
 }
 
 int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int n_params,
             int k_max, int max_blocks, int *block_k, int *block_qubits, double *block_mats,
             int *block_gates, int *n_blocks) {
-    (void)n_qubits; (void)ops; (void)n_ops; (void)params; (void)n_params; (void)k_max;
-    (void)max_blocks; (void)block_k; (void)block_qubits; (void)block_mats; (void)block_gates;
-    (void)n_blocks;
-    return fail(SV_EUNSUPPORTED, "sv_fuse: not built yet");
+    if (n_qubits < 1 || n_qubits > 40) return fail(SV_EINVAL, "n_qubits must be in [1, 40]");
+    if (k_max < 1 || k_max > 5) return fail(SV_EINVAL, "k_max must be in [1, 5]");
+    if (!n_blocks || max_blocks < 0 || (max_blocks > 0 && (!block_k || !block_qubits || !block_mats || !block_gates)))
+        return fail(SV_EINVAL, "NULL output");
+    std::vector<Gate> gs;
+    int rc = parse_ops(nullptr, n_qubits, ops, n_ops, params, n_params, gs);
+    if (rc) return rc;
+    for (const Gate &g : gs)
+        if (__builtin_popcountll(g.qmask()) > k_max)
+            return fail(SV_EINVAL, "a gate touches more qubits than k_max");
+    std::vector<Block> bs = fuse(gs, k_max);
+    *n_blocks = (int)bs.size();
+    if ((int)bs.size() > max_blocks) return fail(SV_EINVAL, "more blocks than max_blocks");
+    for (size_t b = 0; b < bs.size(); ++b) {
+        const Block &B = bs[b];
+        const int D = 1 << B.k;
+        block_k[b] = B.k;
+        block_gates[b] = B.n_gates;
+        for (int j = 0; j < 5; ++j) block_qubits[b * 5 + j] = j < B.k ? B.q[j] : -1;
+        double *m = block_mats + b * 2 * 32 * 32;
+        for (int i = 0; i < D * D; ++i) {
+            m[2 * i] = B.M[i].real();
+            m[2 * i + 1] = B.M[i].imag();
+        }
+    }
+    return SV_OK;
 }
 
 int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
                  int k_max, int prec, int *n_blocks_out) {
-    (void)h; (void)ops; (void)n_ops; (void)params; (void)n_params; (void)k_max; (void)prec;
-    (void)n_blocks_out;
-    return fail(SV_EUNSUPPORTED, "sv_run_fused: not built yet");
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (k_max < 1 || k_max > 5) return fail(SV_EINVAL, "k_max must be in [1, 5]");
+    if (prec != SV_PREC_NATIVE && prec != SV_PREC_FP32 && prec != SV_PREC_SPLIT_BF16)
+        return fail(SV_EINVAL, "unknown precision");
+    std::vector<Gate> gs;
+    int rc = parse_ops(h, h->n, ops, n_ops, params, n_params, gs);
+    if (rc) return rc;
+    const int kk = std::min(k_max, h->n);
+    for (const Gate &g : gs)
+        if (__builtin_popcountll(g.qmask()) > kk)
+            return fail(SV_EINVAL, "a gate touches more qubits than k_max");
+    std::vector<Block> bs = fuse(gs, kk);
+    // stage every dense block once, then launch in order
+    std::vector<size_t> offs(bs.size(), 0);
+    std::vector<char> mf(bs.size(), 0);
+    size_t total = 0;
+    // 1- and 2-qubit blocks use the streamed kernels, except two-qubit blocks
+    // with a target inside a complex64 vector, which take the dense path
+    std::vector<char> streamed(bs.size(), 0);
+    for (size_t b = 0; b < bs.size(); ++b)
+        streamed[b] = bs[b].k <= 2 && !needs_tile(h, block_gate(bs[b]));
+    for (size_t b = 0; b < bs.size(); ++b) {
+        if (streamed[b]) continue;
+        mf[b] = mfma_ok(h, bs[b].k, prec);
+        offs[b] = total;
+        total += block_stage_bytes(h, bs[b].k, mf[b], prec);
+    }
+    if (total) {
+        if ((rc = ensure_arena(h, total))) return rc;
+        if ((rc = stage_wait(h))) return rc;
+        for (size_t b = 0; b < bs.size(); ++b)
+            if (!streamed[b]) stage_block(h, bs[b].M.data(), bs[b].k, mf[b], prec, offs[b]);
+        if ((rc = upload_arena(h, total))) return rc;
+    }
+    for (size_t b = 0; b < bs.size(); ++b) {
+        if (streamed[b]) {
+            if ((rc = apply_one(h, block_gate(bs[b])))) return rc;
+        } else if ((rc = launch_block(h, bs[b].k, bs[b].q, mf[b], prec, offs[b]))) {
+            return rc;
+        }
+    }
+    if (n_blocks_out) *n_blocks_out = (int)bs.size();
+    return SV_OK;
 }
 
 int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, const double *params,

@@ -103,6 +103,9 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileGate *dev_gates,
                        int n_gates, hipStream_t s);
 int tile_max_qubits(int dtype);
+hipError_t launch_dense(void *amps, int n, int dtype, const TileSpec &sp, int k, const int *qubits,
+                        const void *dev_mat, int prec, hipStream_t s);
+int fused_tile_qubits(int dtype);
 
 hipError_t launch_probabilities(const void *amps, int n, int dtype, void *dev_out,
                                 double *dev_partials, int n_partials, double *dev_total,

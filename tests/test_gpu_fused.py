@@ -1,0 +1,100 @@
+"""GPU parity of dense fused blocks (native, FP32 MFMA, split-BF16 MFMA)
+against the FP64 oracle.
+
+Tolerances.  A block output is a 2^k-term sum; in FP32 its rounding error
+is at most 2^k * 4 eps32 times the group's norm, so a normalised state moves
+by at most that in 2-norm per block.  Split-BF16 represents each FP32
+operand as hi + lo with relative error <= 2^-17 per operand and drops the
+lo*lo product (<= 2^-18), so each product is within 2^-15 relative and a
+block output within 2^k * 2^-15 of the group norm.  Every run also checks
+the fidelity target 1 - F <= 1e-6; complex128 blocks are held to 1e-12."""
+
+import math
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+from helpers import C128_ATOL, EPS32, fidelity, random_state
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1805_00988_amd as sv  # noqa: E402
+
+O.build(force=False)
+
+NP_DT = {"c128": np.complex128, "c64": np.complex64}
+PRECS = {"native": sv.SV_PREC_NATIVE, "fp32": sv.SV_PREC_FP32, "bf16x3": sv.SV_PREC_SPLIT_BF16}
+
+
+def block_bound(k, prec, n_blocks=1):
+    per = (2 ** k) * (4 * EPS32 if prec in ("native", "fp32") else 2.0 ** -15)
+    return per * n_blocks
+
+
+def check(got, ref, dtype, prec, k, n_blocks=1):
+    got = got.astype(np.complex128)
+    err = float(np.max(np.abs(got - ref)))
+    if dtype == "c128":
+        assert err <= C128_ATOL, err
+    else:
+        assert err <= block_bound(k, prec, n_blocks), (err, block_bound(k, prec, n_blocks))
+        assert 1.0 - fidelity(got, ref) <= 1e-6
+    return err
+
+
+def start(n, dtype, seed):
+    psi0 = random_state(n, seed)
+    st = sv.State(n, dtype)
+    st.amps.copy_(torch.from_numpy(psi0.astype(NP_DT[dtype])))
+    return st, psi0.astype(NP_DT[dtype]).astype(np.complex128)
+
+
+@pytest.mark.parametrize("dtype,prec", [("c128", "native"), ("c64", "native"), ("c64", "fp32"),
+                                        ("c64", "bf16x3")])
+@pytest.mark.parametrize("n", [10, 14, 17])
+def test_single_block_random_unitary(dtype, prec, n):
+    rng = np.random.default_rng(n)
+    ks = [1, 2, 3, 4, 5] if prec == "native" else [4, 5]
+    qubit_sets = []
+    for k in ks:
+        qubit_sets.append(list(range(k)))                              # lowest qubits
+        qubit_sets.append(list(range(n - k, n)))                       # highest
+        qubit_sets.append([int(q) for q in rng.choice(n, size=k, replace=False)])  # scattered, unsorted
+    for i, qs in enumerate(qubit_sets):
+        k = len(qs)
+        U = C.random_unitary(1 << k, rng)
+        st, psi = start(n, dtype, seed=i)
+        st.apply_fused(U, qs, PRECS[prec])
+        O.apply_kq(psi, n, qs, U)
+        check(st.numpy(), psi, dtype, prec, k)
+
+
+@pytest.mark.parametrize("dtype,prec", [("c128", "native"), ("c64", "native"), ("c64", "fp32"),
+                                        ("c64", "bf16x3")])
+@pytest.mark.parametrize("k", [4, 5])
+@pytest.mark.parametrize("n", [12, 16, 18])
+def test_run_fused_config2_recipe(dtype, prec, k, n):
+    """Config-2 recipe (1q layer + CZ on random pairs) at reduced size."""
+    circ = C.config2(n=n, seed=n + k, depth=12)
+    st = sv.State(n, dtype)
+    nb = st.run_fused(circ.gates, k_max=k, prec=PRECS[prec])
+    assert 0 < nb < len(circ.gates)
+    check(st.numpy(), O.run(circ), dtype, prec, k, nb)
+
+
+@pytest.mark.parametrize("dtype,prec", [("c128", "native"), ("c64", "fp32"), ("c64", "bf16x3")])
+def test_run_fused_qft_and_cnot_circuits(dtype, prec):
+    for circ in (C.qft_circuit(15, 12345), C.random_circuit(15, 10, 3, "X"), C.config0(1)):
+        st = sv.State(circ.n, dtype).set_basis(circ.basis)
+        nb = st.run_fused(circ.gates, k_max=5, prec=PRECS[prec])
+        check(st.numpy(), O.run(circ), dtype, prec, 5, nb)
+
+
+def test_mfma_rejected_for_complex128():
+    st = sv.State(12, "c128")
+    with pytest.raises(sv.SVError):
+        st.apply_fused(np.eye(16), [0, 1, 2, 3], sv.SV_PREC_FP32)
