@@ -34,6 +34,8 @@ struct sv_state {
         double bytes;
         hipEvent_t a, b;
     };
+    double *d_scratch = nullptr;      // adjoint partial sums
+    size_t scratch_cap = 0;           // in doubles
     bool timing = false;
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -669,6 +671,44 @@ static int parse_ops(const sv_state *h, int n, const sv_op *ops, int n_ops, cons
     return SV_OK;
 }
 
+
+// ================================================================ adjoint
+static Gate dagger(const Gate &g) {
+    Gate d = g;
+    const int D = 1 << g.k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            d.U[2 * (c * D + r)] = g.U[2 * (r * D + c)];
+            d.U[2 * (c * D + r) + 1] = -g.U[2 * (r * D + c) + 1];
+        }
+    return d;
+}
+
+// Probe M and factor f of a parametrised gate: dU/dtheta = c M U gives the
+// gradient term f * Im <lam| M |psi> (R_P = exp(-i theta P/2): M = P, f = 1;
+// U1 = diag(1, e^{i theta}): M = |1><1|, f = -2).
+static bool probe_of(int kind, double *M, double *f) {
+    for (int i = 0; i < 8; ++i) M[i] = 0.0;
+    switch (kind) {
+    case SV_GATE_RX: M[2] = 1; M[4] = 1; *f = 1.0; return true;
+    case SV_GATE_RY: M[3] = -1; M[5] = 1; *f = 1.0; return true;
+    case SV_GATE_RZ: M[0] = 1; M[6] = -1; *f = 1.0; return true;
+    case SV_GATE_U1: M[6] = 1; *f = -2.0; return true;
+    default: return false;
+    }
+}
+
+static int ensure_scratch(sv_state *h, size_t doubles) {
+    if (doubles <= h->scratch_cap) return SV_OK;
+    SV_HIP(hipStreamSynchronize(h->stream));
+    if (h->d_scratch) SV_HIP(hipFree(h->d_scratch));
+    h->d_scratch = nullptr;
+    h->scratch_cap = 0;
+    SV_HIP(hipMalloc((void **)&h->d_scratch, doubles * sizeof(double)));
+    h->scratch_cap = doubles;
+    return SV_OK;
+}
+
 } // namespace sv
 
 using namespace sv;
@@ -742,6 +782,7 @@ int sv_free(sv_handle h) {
     if (h->owned && h->amps) hipFree(h->amps);
     if (h->d_red) hipFree(h->d_red);
     if (h->h_result) hipHostFree(h->h_result);
+    if (h->d_scratch) hipFree(h->d_scratch);
     if (h->d_arena) hipFree(h->d_arena);
     if (h->h_arena) hipHostFree(h->h_arena);
     if (h->stage_done) hipEventDestroy(h->stage_done);
@@ -982,9 +1023,81 @@ int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params,
 int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, const double *params,
                     int n_params, int n_terms, const uint64_t *z_masks, const double *coeffs,
                     double *host_loss, double *host_grad) {
-    (void)h; (void)lam; (void)ops; (void)n_ops; (void)params; (void)n_params; (void)n_terms;
-    (void)z_masks; (void)coeffs; (void)host_loss; (void)host_grad;
-    return fail(SV_EUNSUPPORTED, "sv_adjoint_grad: not built yet");
+    if (!h || !lam) return fail(SV_EINVAL, "NULL handle");
+    if (h == lam || h->amps == lam->amps) return fail(SV_EINVAL, "work handle must be distinct");
+    if (h->n != lam->n || h->dtype != lam->dtype) return fail(SV_EINVAL, "work handle differs in size or dtype");
+    if (n_terms < 1 || n_terms > kMaxTerms) return fail(SV_EINVAL, "n_terms must be in [1, 64]");
+    if (!z_masks || !coeffs || !host_loss) return fail(SV_EINVAL, "NULL argument");
+    if (n_params < 0 || (n_params > 0 && (!params || !host_grad))) return fail(SV_EINVAL, "bad parameter vector");
+    for (int j = 0; j < n_terms; ++j)
+        if (h->n < 64 && (z_masks[j] >> h->n) != 0) return fail(SV_EINVAL, "Z mask has bits >= n");
+    std::vector<Gate> gs;
+    int rc = parse_ops(h, h->n, ops, n_ops, params, n_params, gs);
+    if (rc) return rc;
+    int n_param_gates = 0;
+    for (int i = 0; i < n_ops; ++i) {
+        if (ops[i].param_index < 0) continue;
+        double M[8], f;
+        if (ops[i].kind == SV_GATE_MATRIX || !probe_of(ops[i].kind, M, &f))
+            return fail(SV_EINVAL, "op " + std::to_string(i) + ": only RX RY RZ U1 can carry a parameter");
+        ++n_param_gates;
+    }
+    const int B = adjoint_blocks();
+    const size_t slots = (size_t)n_param_gates + 1;
+    if ((rc = ensure_scratch(h, slots * B + slots))) return rc;
+    double *partials = h->d_scratch, *sums = h->d_scratch + slots * B;
+    hipStream_t saved = lam->stream;
+    SV_HIP(hipStreamSynchronize(saved));
+    lam->stream = h->stream; // every launch of the sweep is ordered on h's stream
+    auto restore = [&](int code) {
+        lam->stream = saved;
+        return code;
+    };
+    {
+        Timed tm(h, K_ADJOINT, 2.0 * state_bytes(h));
+        hipError_t e = launch_adjoint_init(h->amps, lam->amps, h->n, h->dtype, n_terms, z_masks, coeffs,
+                                           partials, h->stream);
+        if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_init"));
+    }
+    std::vector<int> slot_param(slots, -1);
+    std::vector<double> slot_factor(slots, 0.0);
+    std::vector<Gate> pending;
+    auto flush = [&]() -> int {
+        if (pending.empty()) return SV_OK;
+        int r = run_gates(h, pending, SV_RUN_TILED);
+        if (!r) r = run_gates(lam, pending, SV_RUN_TILED);
+        pending.clear();
+        return r;
+    };
+    int slot = 1;
+    for (int g = n_ops - 1; g >= 0; --g) {
+        if (ops[g].param_index < 0) {
+            pending.push_back(dagger(gs[g]));
+            continue;
+        }
+        if ((rc = flush())) return restore(rc);
+        double M[8], f;
+        probe_of(ops[g].kind, M, &f);
+        const Gate d = dagger(gs[g]);
+        Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(d.ctrl)));
+        hipError_t e = launch_adjoint_param(h->amps, lam->amps, h->n, h->dtype, d.t[0], d.ctrl, d.U, M,
+                                            partials + (size_t)slot * B, h->stream);
+        if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_param"));
+        slot_param[slot] = ops[g].param_index;
+        slot_factor[slot] = f;
+        ++slot;
+    }
+    if ((rc = flush())) return restore(rc);
+    hipError_t e = launch_sum_slots(partials, (int)slots, B, sums, h->stream);
+    if (e != hipSuccess) return restore(hip_fail(e, "launch_sum_slots"));
+    std::vector<double> out(slots);
+    e = hipMemcpyAsync(out.data(), sums, slots * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return restore(hip_fail(e, "adjoint result copy"));
+    *host_loss = out[0];
+    for (int p = 0; p < n_params; ++p) host_grad[p] = 0.0;
+    for (size_t sl = 1; sl < slots; ++sl) host_grad[slot_param[sl]] += slot_factor[sl] * out[sl];
+    return restore(SV_OK);
 }
 
 } // extern "C"

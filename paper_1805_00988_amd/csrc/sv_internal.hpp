@@ -116,4 +116,14 @@ hipError_t launch_expectation(const void *amps, int n, int dtype, int n_terms,
                               int n_partials, double *dev_total, hipStream_t s);
 constexpr int kReduceBlocks = 1024;
 
+int adjoint_blocks();
+hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int n_terms,
+                               const uint64_t *masks, const double *coeffs, double *partials,
+                               hipStream_t s);
+hipError_t launch_adjoint_param(void *psi, void *lam, int n, int dtype, int t, uint64_t ctrl,
+                                const double *udag, const double *probe, double *partials,
+                                hipStream_t s);
+hipError_t launch_sum_slots(const double *partials, int n_slots, int n_blocks, double *out,
+                            hipStream_t s);
+
 } // namespace sv
