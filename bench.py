@@ -124,8 +124,8 @@ def main():
         for r in regs:
             h = r["state"].handle
             _lib.check(lib.sv_set_basis(h, r["qft"].basis))
-            _lib.check(lib.sv_run(h, r["ops_qft"], len(r["qft"].gates), None, 0, mode))
-            _lib.check(lib.sv_run(h, r["ops_rnd"], len(r["rnd"].gates), None, 0, mode))
+            _lib.check(lib.sv_run(h, sv._opptr(r["ops_qft"]), len(r["qft"].gates), None, 0, mode))
+            _lib.check(lib.sv_run(h, sv._opptr(r["ops_rnd"]), len(r["rnd"].gates), None, 0, mode))
             _lib.check(lib.sv_probabilities(h, ctypes.c_void_p(r["probs"].data_ptr()),
                                             ctypes.byref(norm)))
             _lib.check(lib.sv_expectation(h, 1, zmask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),

@@ -190,6 +190,37 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops,
                     const double *params, int n_params, int n_terms, const uint64_t *z_masks,
                     const double *coeffs, double *host_loss, double *host_grad);
 
+/* Batches of independent circuits (one persistent launch).
+ *
+ * sv_batch_create compiles n_circuits circuits: circuit i acts on its own
+ * register of widths[i] qubits (4..30 for SV_C64, 3..30 for SV_C128), starts
+ * in |0...0> and runs ops[op_offsets[i] .. op_offsets[i+1]) (op_offsets has
+ * n_circuits + 1 entries, op_offsets[0] = 0; params as in sv_run).  The
+ * result of circuit i is <psi_i| Z^{z_mask} |psi_i> in FP64.  Circuits whose
+ * state fits in one workgroup's LDS never touch HBM; wider ones keep their
+ * state in device memory.  The whole batch is captured once as a HIP graph
+ * holding one persistent kernel whose workgroups take circuits from a device
+ * queue, longest first.  flags: SV_BATCH_KEEP_STATES also stores every final
+ * state (for sv_batch_state).  All work is ordered on hip_stream.
+ * sv_batch_run launches the graph (asynchronous); sv_batch_results waits and
+ * copies the n_circuits results to host memory; sv_batch_output returns
+ * their device address.  sv_batch_tune times the graph for every candidate
+ * tile size (LDS tile of 13, 12 or 11 qubits for complex64; 12, 11, 10 for
+ * complex128), sweep width (3 or 4 register qubits) and grid (1 or 2
+ * workgroups per CU), reps launches each, and keeps the fastest; the chosen
+ * values and their time per launch are written to the non-NULL outputs. */
+enum sv_batch_flags { SV_BATCH_KEEP_STATES = 1 };
+typedef struct sv_batch *sv_batch_handle;
+int sv_batch_create(int n_circuits, const int *widths, const int64_t *op_offsets, const sv_op *ops,
+                    const double *params, int n_params, int dtype, uint64_t z_mask, int flags,
+                    void *hip_stream, sv_batch_handle *out);
+int sv_batch_run(sv_batch_handle b);
+int sv_batch_results(sv_batch_handle b, double *host_out);
+void *sv_batch_output(sv_batch_handle b);
+int sv_batch_state(sv_batch_handle b, int i, void *host_out);
+int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *grid, double *best_ms);
+int sv_batch_free(sv_batch_handle b);
+
 /* Per-launch timing of a handle's kernels, for measurement: with timing on,
  * every kernel launch of the handle is bracketed by two HIP events recorded
  * on the handle's stream.  sv_timing(h, 1) starts (and clears) a record,

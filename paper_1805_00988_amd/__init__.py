@@ -22,7 +22,7 @@ __all__ = ["State", "sv_alloc", "sv_free", "sv_set_basis", "sv_apply_gate", "sv_
            "sv_probabilities", "sv_expectation", "sv_run", "sv_fuse", "sv_run_fused",
            "sv_adjoint_grad", "sv_state_bytes", "ops_from_gates", "SV_C64", "SV_C128",
            "SV_PREC_NATIVE", "SV_PREC_FP32", "SV_PREC_SPLIT_BF16", "SV_RUN_PER_GATE",
-           "SV_RUN_TILED", "SVError"]
+           "SV_RUN_TILED", "SVError", "Batch"]
 
 
 def _torch():
@@ -119,28 +119,38 @@ def sv_expectation(h, z_masks: Sequence[int], coeffs: Sequence[float]) -> float:
     return out.value
 
 
-def ops_from_gates(gates) -> ctypes.Array:
-    """sv_op array from symbolic gates (name, targets, controls, theta,
-    param, matrix) as produced by the circuit generators."""
-    arr = (sv_op * max(1, len(gates)))()
+SV_OP_DTYPE = np.dtype([("kind", np.int32), ("n_targets", np.int32), ("targets", np.int32, (2,)),
+                        ("ctrl_mask", np.uint64), ("param_index", np.int32), ("reserved", np.int32),
+                        ("theta", np.float64), ("matrix", np.float64, (32,))])
+assert SV_OP_DTYPE.itemsize == ctypes.sizeof(sv_op)
+
+
+def ops_from_gates(gates) -> np.ndarray:
+    """sv_op records (numpy structured array with the C layout) from symbolic
+    gates (name, targets, controls, theta, param, matrix)."""
+    n = len(gates)
+    arr = np.zeros(max(1, n), dtype=SV_OP_DTYPE)
+    if n == 0:
+        return arr
+    arr["kind"][:n] = [GATE_KINDS[g.name] for g in gates]
+    arr["n_targets"][:n] = [len(g.targets) for g in gates]
+    t = arr["targets"]
+    t[:n, 0] = [g.targets[0] for g in gates]
+    t[:n, 1] = [g.targets[1] if len(g.targets) > 1 else 0 for g in gates]
+    arr["ctrl_mask"][:n] = [sum(1 << c for c in g.controls) for g in gates]
+    arr["param_index"][:n] = [g.param for g in gates]
+    arr["theta"][:n] = [g.theta for g in gates]
     for i, g in enumerate(gates):
-        op = arr[i]
-        op.kind = GATE_KINDS[g.name]
-        op.n_targets = len(g.targets)
-        for j, q in enumerate(g.targets[:2]):
-            op.targets[j] = q
-        mask = 0
-        for c in g.controls:
-            mask |= 1 << c
-        op.ctrl_mask = mask
-        op.param_index = g.param
-        op.theta = g.theta
         if g.name == "U":
             m = _mat(g.matrix)
             if m.size > 32:
                 raise ValueError("sv_op holds at most a 4x4 matrix")
-            ctypes.memmove(op.matrix, m.ctypes.data, m.nbytes)
+            arr["matrix"][i, :m.size] = m
     return arr
+
+
+def _opptr(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.POINTER(sv_op))
 
 
 def _params(params) -> tuple:
@@ -153,7 +163,7 @@ def _params(params) -> tuple:
 def sv_run(h, gates, params=None, mode: int = SV_RUN_TILED) -> None:
     ops = ops_from_gates(gates)
     pp, n_p, keep = _params(params)
-    _lib.check(_lib.load().sv_run(h, ops, len(gates), pp, n_p, int(mode)))
+    _lib.check(_lib.load().sv_run(h, _opptr(ops), len(gates), pp, n_p, int(mode)))
 
 
 def sv_fuse(n_qubits: int, gates, k_max: int, params=None, max_blocks: Optional[int] = None):
@@ -167,7 +177,7 @@ def sv_fuse(n_qubits: int, gates, k_max: int, params=None, max_blocks: Optional[
     bm = np.zeros(cap * 2 * 32 * 32, np.float64)
     bg = np.zeros(cap, np.int32)
     nb = ctypes.c_int()
-    _lib.check(_lib.load().sv_fuse(n_qubits, ops, len(gates), pp, n_p, k_max, cap, _iptr(bk),
+    _lib.check(_lib.load().sv_fuse(n_qubits, _opptr(ops), len(gates), pp, n_p, k_max, cap, _iptr(bk),
                                    _iptr(bq), _dptr(bm), _iptr(bg), ctypes.byref(nb)))
     out = []
     for b in range(nb.value):
@@ -182,7 +192,7 @@ def sv_run_fused(h, gates, k_max: int, prec: int, params=None) -> int:
     ops = ops_from_gates(gates)
     pp, n_p, keep = _params(params)
     nb = ctypes.c_int()
-    _lib.check(_lib.load().sv_run_fused(h, ops, len(gates), pp, n_p, int(k_max), int(prec),
+    _lib.check(_lib.load().sv_run_fused(h, _opptr(ops), len(gates), pp, n_p, int(k_max), int(prec),
                                         ctypes.byref(nb)))
     return nb.value
 
@@ -194,9 +204,70 @@ def sv_adjoint_grad(h, lam, gates, params, z_masks, coeffs):
     c = np.ascontiguousarray(coeffs, dtype=np.float64)
     grad = np.zeros(len(p), np.float64)
     loss = ctypes.c_double()
-    _lib.check(_lib.load().sv_adjoint_grad(h, lam, ops, len(gates), _dptr(p), len(p), len(m),
+    _lib.check(_lib.load().sv_adjoint_grad(h, lam, _opptr(ops), len(gates), _dptr(p), len(p), len(m),
                                            _u64ptr(m), _dptr(c), ctypes.byref(loss), _dptr(grad)))
     return loss.value, grad
+
+
+# ------------------------------------------------------------------ Batch
+
+class Batch:
+    """Thousands of independent circuits run by one persistent kernel launch
+    captured in a HIP graph (sv_batch_*).  ``circuits`` are objects with
+    ``n`` and ``gates`` (parametrised gates must carry their angle in theta);
+    the result of each circuit is <Z^{z_mask}>."""
+
+    def __init__(self, circuits, dtype="c64", z_mask: int = 1, keep_states: bool = False,
+                 stream=None):
+        L = _lib.load()
+        self.n = len(circuits)
+        self.dtype = _dtype_code(dtype)
+        self.widths = np.ascontiguousarray([c.n for c in circuits], dtype=np.int32)
+        gates = [g for c in circuits for g in c.gates]
+        offs = np.zeros(self.n + 1, dtype=np.int64)
+        offs[1:] = np.cumsum([len(c.gates) for c in circuits])
+        ops = ops_from_gates(gates)
+        ops["param_index"] = -1  # angles are carried in theta
+        h = ctypes.c_void_p()
+        s = stream if stream is not None else _current_stream()
+        _lib.check(L.sv_batch_create(self.n, _iptr(self.widths),
+                                     offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _opptr(ops), None, 0,
+                                     self.dtype, int(z_mask), _lib.SV_BATCH_KEEP_STATES if keep_states else 0,
+                                     s, ctypes.byref(h)))
+        self.handle = h
+
+    def run(self) -> "Batch":
+        _lib.check(_lib.load().sv_batch_run(self.handle))
+        return self
+
+    def results(self) -> np.ndarray:
+        out = np.zeros(self.n, np.float64)
+        _lib.check(_lib.load().sv_batch_results(self.handle, _dptr(out)))
+        return out
+
+    def state(self, i: int) -> np.ndarray:
+        dt = np.complex64 if self.dtype == SV_C64 else np.complex128
+        out = np.zeros(1 << int(self.widths[i]), dt)
+        _lib.check(_lib.load().sv_batch_state(self.handle, int(i), ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def tune(self, reps: int = 2):
+        m, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        t = ctypes.c_double()
+        _lib.check(_lib.load().sv_batch_tune(self.handle, int(reps), ctypes.byref(m), ctypes.byref(w),
+                                             ctypes.byref(g), ctypes.byref(t)))
+        return {"tile_qubits": m.value, "sweep_width": w.value, "grid": g.value, "ms": t.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _lib.check(_lib.load().sv_batch_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ State

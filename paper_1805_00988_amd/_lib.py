@@ -22,8 +22,11 @@ GATE_KINDS = {"H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6,
 
 EXPORTED = ("sv_state_bytes", "sv_alloc", "sv_free", "sv_set_basis", "sv_set_stream", "sv_sync",
             "sv_data", "sv_apply_gate", "sv_apply_fused", "sv_probabilities", "sv_expectation",
-            "sv_run", "sv_fuse", "sv_run_fused", "sv_adjoint_grad", "sv_timing",
-            "sv_timing_read", "sv_last_error", "sv_version")
+            "sv_run", "sv_fuse", "sv_run_fused", "sv_adjoint_grad", "sv_batch_create",
+            "sv_batch_run", "sv_batch_results", "sv_batch_output", "sv_batch_state",
+            "sv_batch_tune", "sv_batch_free", "sv_timing", "sv_timing_read", "sv_last_error",
+            "sv_version")
+SV_BATCH_KEEP_STATES = 1
 
 
 class sv_op(ctypes.Structure):
@@ -71,6 +74,14 @@ _PROTOS = {
     "sv_fuse": (_I, [_I, _OPP, _I, _DP, _I, _I, _I, _IP, _IP, _DP, _IP, _IP]),
     "sv_run_fused": (_I, [_P, _OPP, _I, _DP, _I, _I, _I, _IP]),
     "sv_adjoint_grad": (_I, [_P, _P, _OPP, _I, _DP, _I, _I, _U64P, _DP, _DP, _DP]),
+    "sv_batch_create": (_I, [_I, _IP, ctypes.POINTER(ctypes.c_int64), _OPP, _DP, _I, _I, _U64, _I,
+                             _P, ctypes.POINTER(_P)]),
+    "sv_batch_run": (_I, [_P]),
+    "sv_batch_results": (_I, [_P, _DP]),
+    "sv_batch_output": (_P, [_P]),
+    "sv_batch_state": (_I, [_P, _I, _P]),
+    "sv_batch_tune": (_I, [_P, _I, _IP, _IP, _IP, _DP]),
+    "sv_batch_free": (_I, [_P]),
     "sv_timing": (_I, [_P, _I]),
     "sv_timing_read": (_I, [_P, ctypes.POINTER(sv_kernel_stat), _I, _IP]),
     "sv_last_error": (ctypes.c_char_p, []),

@@ -8,6 +8,7 @@
 // wavefront load is a contiguous run as long as the target qubit is above the
 // vector width.
 #include "sv_internal.hpp"
+#include "tile_sweep.hpp"
 
 #include <algorithm>
 
@@ -345,13 +346,17 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
 // ------------------------------------------------------------ tile pass
 // A workgroup stages one tile of 2^m amplitudes in LDS: the low qubits
 // 0..L-1 (contiguous runs of 2^L amplitudes in HBM) plus K further qubits.
-// Every gate of the pass acts on tile qubits only; controls outside the tile
-// are constant over a tile and are tested once on its base index.
+// The pass's gates, grouped into register sweeps by the host, are applied
+// to the tile (tile_sweep.hpp); controls outside the tile are constant over a
+// tile and tested once on its base index.
 constexpr int kTileThreads = 512;
 
 int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; } // 64 KiB of LDS
 
-template <typename T>
+// Register qubits per sweep: 16 complex64 or 8 complex128 amplitudes per
+// group (64 and 32 VGPRs), keeping two 512-thread workgroups per CU.
+int sweep_width(int dtype) { return dtype == SV_C64 ? 4 : 3; }
+
 __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t base, uint32_t l) {
     uint64_t g = base | (l & ((1u << sp.L) - 1u));
     uint32_t hi = l >> sp.L;
@@ -363,107 +368,72 @@ __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t bas
     return g;
 }
 
-template <typename T>
-__device__ __forceinline__ cpx<T> gm(const TileGate &G, int i) {
-    return cpx<T>{(T)G.m[2 * i], (T)G.m[2 * i + 1]};
-}
-
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v, TileSpec sp, int m,
+                                                       const TileSweep *__restrict__ sweeps, int n_sweeps,
                                                        const TileGate *__restrict__ gates,
-                                                       int n_gates, uint64_t n_tiles) {
+                                                       uint64_t n_tiles) {
     using V = Vec<T>;
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
-    const uint32_t tsize = 1u << m;
-    const uint32_t tvec = tsize >> V::bits;
+    const uint32_t tvec = (1u << m) >> V::bits;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        // stage in: element l covers local amplitudes l*VA .. l*VA+VA-1 (L >= vector bits)
+        // element l covers local amplitudes l*VA .. l*VA+VA-1 (L >= vector bits)
         for (uint32_t l = threadIdx.x; l < tvec; l += kTileThreads) {
             const uint32_t la = l << V::bits;
-            const typename V::type w = v[tile_global<T>(sp, base, la) >> V::bits];
+            const typename V::type w = v[tile_global(sp, base, la) >> V::bits];
 #pragma unroll
-            for (int k = 0; k < V::amps; ++k) lds[la + k] = V::get(w, k);
+            for (int k = 0; k < V::amps; ++k) lds[lds_phys<T>(la + k)] = V::get(w, k);
         }
         __syncthreads();
-        for (int gi = 0; gi < n_gates; ++gi) {
-            const TileGate &G = gates[gi];
-            if ((base & G.cout) != G.cout) continue; // uniform over the workgroup
-            const uint32_t cin = G.cin;
-            if (G.kind == TG_1Q) {
-                const cpx<T> g0 = gm<T>(G, 0), g1 = gm<T>(G, 1), g2 = gm<T>(G, 2), g3 = gm<T>(G, 3);
-                const int b = G.b0;
-                const uint32_t low = (1u << b) - 1u;
-                for (uint32_t p = threadIdx.x; p < (tsize >> 1); p += kTileThreads) {
-                    const uint32_t a = (p & low) | ((p & ~low) << 1);
-                    if ((a & cin) != cin) continue;
-                    const uint32_t c = a | (1u << b);
-                    const cpx<T> x0 = lds[a], x1 = lds[c];
-                    lds[a] = cfma(g0, x0, cmul(g1, x1));
-                    lds[c] = cfma(g2, x0, cmul(g3, x1));
-                }
-            } else if (G.kind == TG_2Q) {
-                const int b0 = G.b0, b1 = G.b1;
-                const int lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
-                const uint32_t mlo = (1u << lo) - 1u, mhi = (1u << hi) - 1u;
-                for (uint32_t p = threadIdx.x; p < (tsize >> 2); p += kTileThreads) {
-                    uint32_t a = (p & mlo) | ((p & ~mlo) << 1);
-                    a = (a & mhi) | ((a & ~mhi) << 1);
-                    if ((a & cin) != cin) continue;
-                    uint32_t idx[4] = {a, a | (1u << b0), a | (1u << b1), a | (1u << b0) | (1u << b1)};
-                    cpx<T> x[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) x[q] = lds[idx[q]];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        cpx<T> acc = cmul(gm<T>(G, 4 * r), x[0]);
-#pragma unroll
-                        for (int c = 1; c < 4; ++c) acc = cfma(gm<T>(G, 4 * r + c), x[c], acc);
-                        lds[idx[r]] = acc;
-                    }
-                }
-            } else { // TG_DIAG: amplitude *= d0 (bit b0 clear) or d1 (bit b0 set)
-                const cpx<T> d0 = gm<T>(G, 0), d1 = gm<T>(G, 1);
-                const int b = G.b0;
-                for (uint32_t l = threadIdx.x; l < tsize; l += kTileThreads) {
-                    if ((l & cin) != cin) continue;
-                    lds[l] = cmul(((l >> b) & 1u) ? d1 : d0, lds[l]);
-                }
-            }
-            __syncthreads();
-        }
+        tile_run_sweeps<T, W>(lds, m, base, sweeps, n_sweeps, gates);
         for (uint32_t l = threadIdx.x; l < tvec; l += kTileThreads) {
             const uint32_t la = l << V::bits;
             typename V::type w;
 #pragma unroll
-            for (int k = 0; k < V::amps; ++k) V::put(w, k, lds[la + k]);
-            v[tile_global<T>(sp, base, la) >> V::bits] = w;
+            for (int k = 0; k < V::amps; ++k) V::put(w, k, lds[lds_phys<T>(la + k)]);
+            v[tile_global(sp, base, la) >> V::bits] = w;
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileGate *dev_gates,
-                       int n_gates, hipStream_t s) {
+template <typename T, int W>
+static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m, const TileSweep *sw,
+                          int n_sweeps, const TileGate *g, uint64_t n_tiles, size_t lds, hipStream_t s) {
+    (void)hipFuncSetAttribute((const void *)k_tile<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 2048);
+    k_tile<T, W><<<grid, kTileThreads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles);
+}
+
+hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
+                       int n_sweeps, const TileGate *dev_gates, hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
-    if (m > n || m > tile_max_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh)
+    if (m > n || m > tile_max_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh || m < 1)
         return hipErrorInvalidValue;
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
-    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 2048);
-    if (dtype == SV_C64) {
-        (void)hipFuncSetAttribute((const void *)k_tile<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-        k_tile<float><<<dim3(grid), dim3(kTileThreads), lds, s>>>((float4 *)amps, spec, m, dev_gates, n_gates, n_tiles);
-    } else {
-        (void)hipFuncSetAttribute((const void *)k_tile<double>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_tile<double><<<dim3(grid), dim3(kTileThreads), lds, s>>>((double2 *)amps, spec, m, dev_gates, n_gates, n_tiles);
+    const int W = std::min(m, sweep_width(dtype));
+#define SV_TILE_CASE(WW)                                                                           \
+    if (W == WW) {                                                                                 \
+        if (dtype == SV_C64)                                                                       \
+            launch_tile_t<float, WW>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,     \
+                                     n_tiles, lds, s);                                             \
+        else                                                                                       \
+            launch_tile_t<double, WW>((double2 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,   \
+                                      n_tiles, lds, s);                                            \
+        return hipGetLastError();                                                                  \
     }
-    return hipGetLastError();
+    SV_TILE_CASE(4)
+    SV_TILE_CASE(3)
+    SV_TILE_CASE(2)
+    SV_TILE_CASE(1)
+#undef SV_TILE_CASE
+    return hipErrorInvalidValue;
 }
 
 } // namespace sv

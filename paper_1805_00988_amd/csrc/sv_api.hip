@@ -208,8 +208,7 @@ static int upload_arena(sv_state *h, size_t bytes) {
     return SV_OK;
 }
 
-static TileGate *h_gates(sv_state *h) { return reinterpret_cast<TileGate *>(h->h_arena); }
-static TileGate *d_gates(sv_state *h) { return reinterpret_cast<TileGate *>(h->d_arena); }
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int stage_wait(sv_state *h) {
     if (h->stage_pending) SV_HIP(hipEventSynchronize(h->stage_done));
@@ -285,49 +284,147 @@ static int local_bit(const TileSpec &sp, int q) {
     return -1;
 }
 
-static void encode_tile_gate(const TileSpec &sp, const Gate &g, TileGate *r) {
-    std::memset(r, 0, sizeof(*r));
-    r->b0 = local_bit(sp, g.t[0]);
-    r->b1 = g.k == 2 ? local_bit(sp, g.t[1]) : 0;
-    uint64_t c = g.ctrl;
-    while (c) {
+// A tile pass compiled for the device: tile layout, register sweeps and the
+// sweeps' gate records (stored consecutively in sweep order).
+struct PassCode {
+    TileSpec sp{};
+    int m = 0;
+    std::vector<TileSweep> sweeps;
+    std::vector<TileGate> gates;
+    size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + gates.size() * sizeof(TileGate); }
+};
+
+static bool is_diag1(const Gate &g) { return g.k == 1 && is_zero(g.U + 2) && is_zero(g.U + 4); }
+
+static bool is_x(const Gate &g) {
+    const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+    return g.k == 1 && std::memcmp(g.U, x, sizeof(x)) == 0;
+}
+
+static void encode_controls(const TileSpec &sp, uint64_t ctrl, TileGate *r) {
+    for (uint64_t c = ctrl; c; c &= c - 1) {
         const int b = __builtin_ctzll(c);
-        c &= c - 1;
         const int lb = local_bit(sp, b);
         if (lb >= 0) r->cin |= 1u << lb;
         else r->cout |= 1ull << b;
     }
-    if (g.k == 2) {
-        r->kind = TG_2Q;
-        std::memcpy(r->m, g.U, sizeof(double) * 32);
-    } else if (is_zero(g.U + 2) && is_zero(g.U + 4)) {
-        r->kind = TG_DIAG;
-        r->m[0] = g.U[0]; r->m[1] = g.U[1]; r->m[2] = g.U[6]; r->m[3] = g.U[7];
-    } else {
-        r->kind = TG_1Q;
-        std::memcpy(r->m, g.U, sizeof(double) * 8);
-    }
 }
 
-static void encode_pass(sv_state *h, const TileSpec &sp, const std::vector<const Gate *> &gs,
-                        size_t slot_offset) {
-    for (size_t i = 0; i < gs.size(); ++i) encode_tile_gate(sp, *gs[i], &h_gates(h)[slot_offset + i]);
+static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qset, const Gate &g) {
+    TileGate r;
+    std::memset(&r, 0, sizeof(r));
+    encode_controls(sp, g.ctrl, &r);
+    auto pos = [&](int q) {
+        const int lb = local_bit(sp, q);
+        for (size_t j = 0; j < qset.size(); ++j)
+            if (qset[j] == lb) return (int)j;
+        return -1;
+    };
+    if (is_diag1(g)) {
+        r.kind = SK_DIAG;
+        r.b0 = local_bit(sp, g.t[0]);
+        r.m[0] = g.U[0]; r.m[1] = g.U[1]; r.m[2] = g.U[6]; r.m[3] = g.U[7];
+        return r;
+    }
+    if (g.k == 1) {
+        r.b0 = pos(g.t[0]);
+        bool real = true;
+        for (int i = 0; i < 4; ++i) real = real && g.U[2 * i + 1] == 0.0;
+        r.kind = is_x(g) ? SK_SWAP : (real ? SK_REAL : SK_GEN);
+        std::memcpy(r.m, g.U, sizeof(double) * 8);
+        return r;
+    }
+    r.kind = SK_2Q;
+    const int p0 = pos(g.t[0]), p1 = pos(g.t[1]);
+    if (p0 < p1) {
+        r.b0 = p0;
+        r.b1 = p1;
+        std::memcpy(r.m, g.U, sizeof(double) * 32);
+    } else { // bit 0 of the matrix index must name the lower position: swap index bits
+        r.b0 = p1;
+        r.b1 = p0;
+        auto sw = [](int i) { return ((i & 1) << 1) | ((i >> 1) & 1); };
+        for (int row = 0; row < 4; ++row)
+            for (int col = 0; col < 4; ++col) {
+                const int src = sw(row) * 4 + sw(col), dst = row * 4 + col;
+                r.m[2 * dst] = g.U[2 * src];
+                r.m[2 * dst + 1] = g.U[2 * src + 1];
+            }
+    }
+    return r;
+}
+
+// Group the pass's gates (in order) into sweeps of at most W register
+// qubits; diagonal one-qubit gates join the current sweep whatever their
+// target, since they act per amplitude.
+static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w) {
+    PassCode pc;
+    pc.sp = sp;
+    pc.m = sp.L + sp.K;
+    const int W = std::min(pc.m, sweep_w);
+    std::vector<int> qset;
+    std::vector<const Gate *> cur;
+    auto close = [&]() {
+        if (cur.empty()) return;
+        for (int b = 0; (int)qset.size() < W && b < pc.m; ++b)
+            if (std::find(qset.begin(), qset.end(), b) == qset.end()) qset.push_back(b);
+        std::sort(qset.begin(), qset.end());
+        TileSweep sw{};
+        sw.n_gates = (int)cur.size();
+        for (int j = 0; j < kSweepW; ++j) sw.qpos[j] = j < W ? qset[j] : 0;
+        pc.sweeps.push_back(sw);
+        for (const Gate *g : cur) pc.gates.push_back(encode_sweep_gate(sp, qset, *g));
+        cur.clear();
+        qset.clear();
+    };
+    for (const Gate *g : gs) {
+        if (is_diag1(*g)) {
+            cur.push_back(g);
+            continue;
+        }
+        std::vector<int> need;
+        for (int j = 0; j < g->k; ++j) {
+            const int lb = local_bit(sp, g->t[j]);
+            if (std::find(qset.begin(), qset.end(), lb) == qset.end()) need.push_back(lb);
+        }
+        if ((int)(qset.size() + need.size()) > W) close();
+        for (int j = 0; j < g->k; ++j) {
+            const int lb = local_bit(sp, g->t[j]);
+            if (std::find(qset.begin(), qset.end(), lb) == qset.end()) qset.push_back(lb);
+        }
+        cur.push_back(g);
+    }
+    close();
+    return pc;
+}
+
+// Write a compiled pass into the host arena at 'off' (256-aligned).
+static void stage_pass(sv_state *h, const PassCode &pc, size_t off) {
+    std::memcpy(h->h_arena + off, pc.sweeps.data(), pc.sweeps.size() * sizeof(TileSweep));
+    std::memcpy(h->h_arena + off + align256(pc.sweeps.size() * sizeof(TileSweep)), pc.gates.data(),
+                pc.gates.size() * sizeof(TileGate));
+}
+
+static int launch_pass(sv_state *h, const PassCode &pc, size_t off) {
+    const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + off);
+    const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + off +
+                                                            align256(pc.sweeps.size() * sizeof(TileSweep)));
+    Timed tm(h, K_TILE, 2.0 * state_bytes(h));
+    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, h->stream));
+    return SV_OK;
 }
 
 static int tile_single(sv_state *h, const Gate &g) {
-    int rc = ensure_arena(h, sizeof(TileGate));
-    if (rc) return rc;
-    rc = stage_wait(h);
-    if (rc) return rc;
     TileSpec sp{};
-    tile_layout(h->n, tile_max_qubits(h->dtype), std::min(h->n, 6), g.tmask(), &sp);
+    tile_layout(h->n, std::min(h->n, tile_max_qubits(h->dtype)), std::min(h->n, 6), g.tmask(), &sp);
     std::vector<const Gate *> one{&g};
-    encode_pass(h, sp, one, 0);
-    rc = upload_arena(h, sizeof(TileGate));
+    const PassCode pc = compile_pass(sp, one, sweep_width(h->dtype));
+    int rc = ensure_arena(h, pc.bytes());
     if (rc) return rc;
-    Timed tm(h, K_TILE, 2.0 * state_bytes(h));
-    SV_HIP(launch_tile(h->amps, h->n, h->dtype, sp, d_gates(h), 1, h->stream));
-    return SV_OK;
+    if ((rc = stage_wait(h))) return rc;
+    stage_pass(h, pc, 0);
+    if ((rc = upload_arena(h, pc.bytes()))) return rc;
+    return launch_pass(h, pc, 0);
 }
 
 // Greedy, commutation-aware grouping: scan the unscheduled gates in order;
@@ -389,25 +486,14 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
     const int mmax = std::min(h->n, tile_max_qubits(h->dtype));
     const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
     std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin);
-    // stage every multi-gate pass's records, upload once, then launch in order
+    // compile every tiled pass, stage all of them, upload once, launch in order
+    std::vector<PassCode> code(passes.size());
+    std::vector<size_t> offs(passes.size(), 0);
     std::vector<char> tiled(passes.size(), 0);
     size_t total = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const Pass &p = passes[pi];
         tiled[pi] = p.gates.size() > 1 || (p.gates.size() == 1 && needs_tile(h, gs[p.gates[0]]));
-        if (tiled[pi]) total += p.gates.size();
-    }
-    if (total) {
-        int rc = ensure_arena(h, total * sizeof(TileGate));
-        if (rc) return rc;
-        rc = stage_wait(h);
-        if (rc) return rc;
-    }
-    std::vector<TileSpec> specs(passes.size());
-    std::vector<size_t> offs(passes.size(), 0);
-    size_t off = 0;
-    for (size_t pi = 0; pi < passes.size(); ++pi) {
-        const Pass &p = passes[pi];
         if (!tiled[pi]) continue;
         uint64_t needed = 0;
         std::vector<const Gate *> ptrs;
@@ -415,26 +501,25 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
             needed |= gs[gi].tmask();
             ptrs.push_back(&gs[gi]);
         }
-        tile_layout(h->n, mmax, lmin, needed, &specs[pi]);
-        encode_pass(h, specs[pi], ptrs, off);
-        offs[pi] = off;
-        off += p.gates.size();
+        TileSpec sp{};
+        tile_layout(h->n, mmax, lmin, needed, &sp);
+        code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype));
+        offs[pi] = total;
+        total += align256(code[pi].bytes());
     }
     if (total) {
-        const int rc = upload_arena(h, total * sizeof(TileGate));
+        int rc = ensure_arena(h, total);
         if (rc) return rc;
+        if ((rc = stage_wait(h))) return rc;
+        for (size_t pi = 0; pi < passes.size(); ++pi)
+            if (tiled[pi]) stage_pass(h, code[pi], offs[pi]);
+        if ((rc = upload_arena(h, total))) return rc;
     }
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const Pass &p = passes[pi];
         if (p.gates.empty()) continue;
-        if (!tiled[pi]) {
-            const int rc = apply_one(h, gs[p.gates[0]]);
-            if (rc) return rc;
-        } else {
-            Timed tm(h, K_TILE, 2.0 * state_bytes(h));
-            SV_HIP(launch_tile(h->amps, h->n, h->dtype, specs[pi], d_gates(h) + offs[pi],
-                               (int)p.gates.size(), h->stream));
-        }
+        const int rc = tiled[pi] ? launch_pass(h, code[pi], offs[pi]) : apply_one(h, gs[p.gates[0]]);
+        if (rc) return rc;
     }
     return SV_OK;
 }
@@ -600,8 +685,6 @@ static bool mfma_ok(const sv_state *h, int k, int prec) {
     return m >= k && ((1u << m) >> k) % rows == 0;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 // Bytes a block needs in the arena (matrix in the state's precision, or the
 // MFMA fragments).
 static size_t block_stage_bytes(const sv_state *h, int k, bool mfma, int prec) {
@@ -707,6 +790,193 @@ static int ensure_scratch(sv_state *h, size_t doubles) {
     SV_HIP(hipMalloc((void **)&h->d_scratch, doubles * sizeof(double)));
     h->scratch_cap = doubles;
     return SV_OK;
+}
+
+
+// ================================================================ batches
+struct BatchProgram {
+    std::vector<BatchCircuit> circuits;
+    std::vector<BatchPass> passes;
+    std::vector<TileSweep> sweeps;
+    std::vector<TileGate> gates;
+    std::vector<int32_t> order;
+    size_t state_bytes = 0;
+};
+
+// Compile every circuit into tile passes for tiles of at most mmax qubits
+// and sweeps of sweep_w register qubits.
+static BatchProgram compile_batch(const std::vector<int> &widths,
+                                  const std::vector<std::vector<Gate>> &circ, int dtype, int mmax,
+                                  int sweep_w, bool keep) {
+    BatchProgram bp;
+    const size_t el = dtype == SV_C64 ? 8 : 16;
+    std::vector<double> cost(widths.size());
+    for (size_t i = 0; i < widths.size(); ++i) {
+        const int w = widths[i];
+        const int m = std::min(w, mmax);
+        const int lmin = std::min(w, dtype == SV_C64 ? 7 : 6);
+        std::vector<Pass> passes;
+        if (w <= mmax) {
+            Pass p;
+            for (size_t g = 0; g < circ[i].size(); ++g) p.gates.push_back((int)g);
+            passes.push_back(p);
+        } else {
+            passes = schedule(circ[i], w, m, lmin);
+        }
+        if (passes.empty()) passes.push_back(Pass{}); // a circuit without gates still reduces |0>
+        BatchCircuit c{};
+        c.w = w;
+        c.n_passes = (int)passes.size();
+        c.pass_off = (int)bp.passes.size();
+        c.keep = keep ? 1 : 0;
+        c.state_off = 0;
+        if (passes.size() > 1 || keep) {
+            c.state_off = (int64_t)bp.state_bytes;
+            bp.state_bytes += align256(((size_t)1 << w) * el);
+        }
+        for (const Pass &p : passes) {
+            uint64_t needed = 0;
+            std::vector<const Gate *> ptrs;
+            for (int gi : p.gates) {
+                needed |= circ[i][gi].tmask();
+                ptrs.push_back(&circ[i][gi]);
+            }
+            TileSpec sp{};
+            if (w <= mmax) {
+                sp.L = w;
+                sp.K = 0;
+            } else {
+                tile_layout(w, m, lmin, needed, &sp);
+            }
+            const PassCode pc = compile_pass(sp, ptrs, sweep_w);
+            BatchPass q{};
+            q.sp = sp;
+            q.n_sweeps = (int)pc.sweeps.size();
+            q.sweep_off = (int)bp.sweeps.size();
+            q.gate_off = (int)bp.gates.size();
+            bp.passes.push_back(q);
+            bp.sweeps.insert(bp.sweeps.end(), pc.sweeps.begin(), pc.sweeps.end());
+            bp.gates.insert(bp.gates.end(), pc.gates.begin(), pc.gates.end());
+        }
+        bp.circuits.push_back(c);
+        cost[i] = std::ldexp((double)(circ[i].size() + 1) * (double)passes.size(), w);
+    }
+    bp.order.resize(widths.size());
+    for (size_t i = 0; i < widths.size(); ++i) bp.order[i] = (int32_t)i;
+    std::stable_sort(bp.order.begin(), bp.order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return bp;
+}
+
+} // namespace sv
+
+struct sv_batch {
+    int n = 0;
+    int dtype = 0;
+    int flags = 0;
+    uint64_t zmask = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int> widths;
+    std::vector<std::vector<sv::Gate>> circ;
+    // device program
+    char *d_prog = nullptr;
+    void *d_states = nullptr;
+    double *d_out = nullptr;
+    unsigned int *d_counter = nullptr;
+    sv::BatchArgs args{};
+    std::vector<int64_t> state_off;
+    std::vector<int> n_passes;
+    int tile_m = 0, sweep_w = 0, grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace sv {
+
+static void batch_release_program(sv_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_prog) (void)hipFree(b->d_prog);
+    if (b->d_states) (void)hipFree(b->d_states);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->d_prog = nullptr;
+    b->d_states = nullptr;
+}
+
+// Build, upload and capture the batch program for (tile_m, sweep_w, grid).
+static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
+    SV_HIP(hipStreamSynchronize(b->stream));
+    batch_release_program(b);
+    const bool keep = (b->flags & SV_BATCH_KEEP_STATES) != 0;
+    BatchProgram bp = compile_batch(b->widths, b->circ, b->dtype, tile_m, sweep_w, keep);
+    const size_t o_c = 0;
+    const size_t o_p = align256(o_c + bp.circuits.size() * sizeof(BatchCircuit));
+    const size_t o_s = align256(o_p + bp.passes.size() * sizeof(BatchPass));
+    const size_t o_g = align256(o_s + bp.sweeps.size() * sizeof(TileSweep));
+    const size_t o_o = align256(o_g + bp.gates.size() * sizeof(TileGate));
+    const size_t total = align256(o_o + bp.order.size() * sizeof(int32_t));
+    size_t free_b = 0, total_b = 0;
+    SV_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (total + bp.state_bytes + (64u << 20) > free_b)
+        return fail(SV_ENOMEM, "batch program and states exceed free device memory");
+    SV_HIP(hipMalloc((void **)&b->d_prog, total));
+    if (bp.state_bytes) SV_HIP(hipMalloc(&b->d_states, bp.state_bytes));
+    std::vector<char> host(total, 0);
+    std::memcpy(host.data() + o_c, bp.circuits.data(), bp.circuits.size() * sizeof(BatchCircuit));
+    std::memcpy(host.data() + o_p, bp.passes.data(), bp.passes.size() * sizeof(BatchPass));
+    std::memcpy(host.data() + o_s, bp.sweeps.data(), bp.sweeps.size() * sizeof(TileSweep));
+    std::memcpy(host.data() + o_g, bp.gates.data(), bp.gates.size() * sizeof(TileGate));
+    std::memcpy(host.data() + o_o, bp.order.data(), bp.order.size() * sizeof(int32_t));
+    SV_HIP(hipMemcpy(b->d_prog, host.data(), total, hipMemcpyHostToDevice));
+    BatchArgs &a = b->args;
+    a.circuits = reinterpret_cast<const BatchCircuit *>(b->d_prog + o_c);
+    a.passes = reinterpret_cast<const BatchPass *>(b->d_prog + o_p);
+    a.sweeps = reinterpret_cast<const TileSweep *>(b->d_prog + o_s);
+    a.gates = reinterpret_cast<const TileGate *>(b->d_prog + o_g);
+    a.order = reinterpret_cast<const int32_t *>(b->d_prog + o_o);
+    a.counter = b->d_counter;
+    a.states = b->d_states;
+    a.out = b->d_out;
+    a.n_circuits = b->n;
+    a.zmask = b->zmask;
+    b->state_off.resize(b->n);
+    b->n_passes.resize(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        b->state_off[i] = bp.circuits[i].state_off;
+        b->n_passes[i] = bp.circuits[i].n_passes;
+    }
+    b->tile_m = tile_m;
+    b->sweep_w = sweep_w;
+    b->grid = grid;
+    // one eager launch (sets kernel attributes, checks the launch), then capture
+    SV_HIP(launch_batch(a, b->dtype, sweep_w, tile_m, grid, b->stream));
+    SV_HIP(hipStreamSynchronize(b->stream));
+    // capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured); the graph is launched on the caller's stream
+    hipStream_t cap = nullptr;
+    SV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e0 = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e0 != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(e0, "hipStreamBeginCapture");
+    }
+    hipError_t e = launch_batch(a, b->dtype, sweep_w, tile_m, grid, cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_fail(e, "launch_batch (capture)");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    b->graph = g;
+    SV_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return SV_OK;
+}
+
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
 }
 
 } // namespace sv
@@ -1098,6 +1368,142 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, con
     for (int p = 0; p < n_params; ++p) host_grad[p] = 0.0;
     for (size_t sl = 1; sl < slots; ++sl) host_grad[slot_param[sl]] += slot_factor[sl] * out[sl];
     return restore(SV_OK);
+}
+
+
+int sv_batch_create(int n_circuits, const int *widths, const int64_t *op_offsets, const sv_op *ops,
+                    const double *params, int n_params, int dtype, uint64_t z_mask, int flags,
+                    void *hip_stream, sv_batch_handle *out) {
+    if (!out) return fail(SV_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (n_circuits < 1 || !widths || !op_offsets) return fail(SV_EINVAL, "bad batch description");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    const int wmin = sweep_width(dtype);
+    if (op_offsets[0] != 0) return fail(SV_EINVAL, "op_offsets[0] must be 0");
+    if (op_offsets[n_circuits] > 0 && !ops) return fail(SV_EINVAL, "NULL ops");
+    int wmax = 0;
+    for (int i = 0; i < n_circuits; ++i) {
+        if (widths[i] < wmin || widths[i] > 30)
+            return fail(SV_EINVAL, "circuit width outside [" + std::to_string(wmin) + ", 30]");
+        if (op_offsets[i + 1] < op_offsets[i]) return fail(SV_EINVAL, "op_offsets must not decrease");
+        wmax = std::max(wmax, widths[i]);
+    }
+    if (wmax < 64 && (z_mask >> wmax) != 0) return fail(SV_EINVAL, "Z mask has bits beyond every width");
+    sv_batch *b = new sv_batch();
+    b->n = n_circuits;
+    b->dtype = dtype;
+    b->flags = flags;
+    b->zmask = z_mask;
+    b->stream = (hipStream_t)hip_stream;
+    b->widths.assign(widths, widths + n_circuits);
+    b->circ.resize(n_circuits);
+    for (int i = 0; i < n_circuits; ++i) {
+        std::vector<Gate> &gs = b->circ[i];
+        const int64_t lo = op_offsets[i], hi = op_offsets[i + 1];
+        gs.resize((size_t)(hi - lo));
+        for (int64_t j = lo; j < hi; ++j) {
+            const int rc = op_to_gate(widths[i], ops[j], params, n_params, &gs[(size_t)(j - lo)]);
+            if (rc) {
+                delete b;
+                return fail(rc, "circuit " + std::to_string(i) + " op " + std::to_string(j - lo) + ": " + g_last_error);
+            }
+        }
+    }
+    hipError_t e;
+    if ((e = hipMalloc((void **)&b->d_out, sizeof(double) * n_circuits)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_counter, 256)) != hipSuccess) {
+        sv_batch_free(b);
+        return hip_fail(e, "sv_batch_create");
+    }
+    const int rc = batch_prepare(b, tile_max_qubits(dtype), sweep_width(dtype), 2 * device_cus());
+    if (rc) {
+        const std::string msg = g_last_error;
+        sv_batch_free(b);
+        return fail(rc, msg);
+    }
+    *out = b;
+    return SV_OK;
+}
+
+int sv_batch_run(sv_batch_handle b) {
+    if (!b || !b->exec) return fail(SV_EINVAL, "NULL or unprepared batch");
+    SV_HIP(hipGraphLaunch(b->exec, b->stream));
+    return SV_OK;
+}
+
+int sv_batch_results(sv_batch_handle b, double *host_out) {
+    if (!b || !host_out) return fail(SV_EINVAL, "NULL argument");
+    SV_HIP(hipMemcpyAsync(host_out, b->d_out, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream));
+    SV_HIP(hipStreamSynchronize(b->stream));
+    return SV_OK;
+}
+
+void *sv_batch_output(sv_batch_handle b) { return b ? b->d_out : nullptr; }
+
+int sv_batch_state(sv_batch_handle b, int i, void *host_out) {
+    if (!b || !host_out || i < 0 || i >= b->n) return fail(SV_EINVAL, "bad argument");
+    if (!(b->flags & SV_BATCH_KEEP_STATES)) return fail(SV_EINVAL, "batch was created without SV_BATCH_KEEP_STATES");
+    const size_t bytes = ((size_t)1 << b->widths[i]) * (b->dtype == SV_C64 ? 8 : 16);
+    SV_HIP(hipStreamSynchronize(b->stream));
+    SV_HIP(hipMemcpy(host_out, (char *)b->d_states + b->state_off[i], bytes, hipMemcpyDeviceToHost));
+    return SV_OK;
+}
+
+int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *grid, double *best_ms) {
+    if (!b) return fail(SV_EINVAL, "NULL batch");
+    if (reps < 1) reps = 1;
+    const int cus = device_cus();
+    const int mtop = tile_max_qubits(b->dtype);
+    const int ws[2] = {3, 4};
+    const int ms[3] = {mtop, mtop - 1, mtop - 2};
+    const int gs[2] = {cus, 2 * cus};
+    double best = 1e300;
+    int bm = mtop, bw = sweep_width(b->dtype), bg = 2 * cus;
+    hipEvent_t e0, e1;
+    SV_HIP(hipEventCreate(&e0));
+    SV_HIP(hipEventCreate(&e1));
+    int rc = SV_OK;
+    for (int wi = 0; wi < 2 && !rc; ++wi)
+        for (int mi = 0; mi < 3 && !rc; ++mi)
+            for (int gi = 0; gi < 2 && !rc; ++gi) {
+                if ((rc = batch_prepare(b, ms[mi], ws[wi], gs[gi]))) break;
+                float ms_run = 0.0f;
+                hipError_t e = hipEventRecord(e0, b->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, b->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms_run, e0, e1);
+                if (e != hipSuccess) {
+                    rc = hip_fail(e, "sv_batch_tune");
+                    break;
+                }
+                const double t = ms_run / reps;
+                if (t < best) {
+                    best = t;
+                    bm = ms[mi];
+                    bw = ws[wi];
+                    bg = gs[gi];
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = batch_prepare(b, bm, bw, bg))) return rc;
+    if (tile_m) *tile_m = bm;
+    if (sweep_w) *sweep_w = bw;
+    if (grid) *grid = bg;
+    if (best_ms) *best_ms = best;
+    return SV_OK;
+}
+
+int sv_batch_free(sv_batch_handle b) {
+    if (!b) return fail(SV_EINVAL, "NULL batch");
+    (void)hipStreamSynchronize(b->stream);
+    batch_release_program(b);
+    if (b->d_out) (void)hipFree(b->d_out);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+    return SV_OK;
 }
 
 } // extern "C"

@@ -70,14 +70,29 @@ __device__ __forceinline__ uint64_t expand(const Enum &e, uint64_t i) {
 // ------------------------------------------------------ tile-pass records
 // A gate applied inside an on-chip tile.  Local bit positions refer to the
 // tile's own index: bits [0, L) are qubits 0..L-1, bit L+i is the i-th extra
-// (high) tile qubit.
-enum TileGateKind : int32_t { TG_1Q = 1, TG_2Q = 2, TG_DIAG = 3 };
+// (high) tile qubit.  Within a sweep (see tile_sweep.hpp) b0/b1 are positions
+// among the sweep's register qubits, except for SK_DIAG, where b0 is the
+// target's local bit.
+enum SweepKind : int32_t {
+    SK_GEN = 1,  // general 2x2 on sweep position b0
+    SK_REAL = 2, // real 2x2 (m[0], m[2], m[4], m[6] hold the entries)
+    SK_DIAG = 3, // diag(d0, d1) on tile bit b0 (any position); m: d0, d1
+    SK_SWAP = 4, // X: exchange the pair
+    SK_2Q = 5,   // 4x4 on sweep positions b0 < b1 (bit 0 of the matrix index <-> b0)
+};
 struct TileGate {
     int32_t kind;
-    int32_t b0, b1;    // local target bits (b1 unused for 1q)
+    int32_t b0, b1;
     uint32_t cin;      // control bits inside the tile (local positions)
     uint64_t cout;     // control bits outside the tile (global positions)
-    double m[32];      // 1q: 4 complex, 2q: 16 complex, diag: d0, d1 (2 complex)
+    double m[32];      // matrix entries, complex interleaved
+};
+
+constexpr int kSweepW = 4; // tile qubits held in registers per sweep (fewer for tiny tiles)
+struct TileSweep {
+    int32_t n_gates;       // gates of this sweep, stored consecutively
+    int32_t qpos[kSweepW]; // ascending local positions held in registers
+    int32_t pad[3];
 };
 
 constexpr int kMaxTileHigh = 8; // extra tile qubits beyond the low block
@@ -100,9 +115,10 @@ hipError_t launch_gate2(void *amps, int n, int dtype, int t0, int t1, uint64_t c
                         const double *U, hipStream_t s);
 hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const double *factor,
                         hipStream_t s);
-hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileGate *dev_gates,
-                       int n_gates, hipStream_t s);
+hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
+                       int n_sweeps, const TileGate *dev_gates, hipStream_t s);
 int tile_max_qubits(int dtype);
+int sweep_width(int dtype);
 hipError_t launch_dense(void *amps, int n, int dtype, const TileSpec &sp, int k, const int *qubits,
                         const void *dev_mat, int prec, hipStream_t s);
 int fused_tile_qubits(int dtype);
@@ -115,6 +131,36 @@ hipError_t launch_expectation(const void *amps, int n, int dtype, int n_terms,
                               const uint64_t *masks, const double *coeffs, double *dev_partials,
                               int n_partials, double *dev_total, hipStream_t s);
 constexpr int kReduceBlocks = 1024;
+
+// ------------------------------------------------------------- batches
+struct BatchCircuit {
+    int32_t w;         // qubits
+    int32_t n_passes;
+    int32_t pass_off;
+    int32_t keep;      // store the final state
+    int64_t state_off; // byte offset of the state in the batch's state buffer
+};
+struct BatchPass {
+    TileSpec sp;
+    int32_t n_sweeps;
+    int32_t sweep_off;
+    int32_t gate_off;
+    int32_t pad;
+};
+struct BatchArgs {
+    const BatchCircuit *circuits;
+    const BatchPass *passes;
+    const TileSweep *sweeps;
+    const TileGate *gates;
+    const int32_t *order;
+    unsigned int *counter;
+    void *states;
+    double *out;
+    int n_circuits;
+    uint64_t zmask;
+};
+hipError_t launch_batch(const BatchArgs &args, int dtype, int sweep_w, int tile_m, int grid,
+                        hipStream_t s);
 
 int adjoint_blocks();
 hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int n_terms,
