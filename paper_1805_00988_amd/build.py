@@ -6,7 +6,9 @@ paper_1805_00988_amd/libsv.so, which the Python binding loads.
 
 from __future__ import annotations
 
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -24,7 +26,24 @@ HIPCC_FLAGS = [
     # packed-FP32 instructions are kept out of all generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # per-kernel register / scratch / occupancy report (parsed into _build/)
+    "-Rpass-analysis=kernel-resource-usage",
 ]
+RESOURCES = os.path.join(OBJ, "kernel_resources.json")
+
+
+def parse_resources(text: str) -> dict:
+    """Kernel resource remarks -> {kernel: {field: int}}."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark: \s*([A-Za-z ]+?)(?: \[[^\]]*\])?: (\d+)", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = int(m.group(2))
+    return out
 
 
 def hipcc() -> str:
@@ -51,12 +70,19 @@ def build(verbose: bool = False) -> str:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
-        if r.stderr.strip() and verbose:
-            print(r.stderr, file=sys.stderr)
-        return obj
+        return obj, parse_resources(r.stderr)
 
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(compile_one, srcs))
+        results = list(ex.map(compile_one, srcs))
+    objs = [o for o, _ in results]
+    resources = {}
+    for _, res in results:
+        resources.update(res)
+    with open(RESOURCES, "w") as f:
+        json.dump(resources, f, indent=1, sort_keys=True)
+    spills = {k: v for k, v in resources.items() if v.get("ScratchSize", 0) > 0}
+    if spills:
+        print(f"warning: kernels using scratch memory: {sorted(spills)}", file=sys.stderr)
     tmp = OUT + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

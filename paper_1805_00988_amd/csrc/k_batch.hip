@@ -66,12 +66,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
         __syncthreads();
         if (qi >= a.n_circuits) break; // uniform: every wave leaves together
         const int ci = a.order[qi];
-        const BatchCircuit c = a.circuits[ci];
+        const BatchCircuit &c = a.circuits[ci]; // read through memory (uniform)
         typename V::type *state = reinterpret_cast<typename V::type *>(
             reinterpret_cast<char *>(a.states) + c.state_off);
         double zacc = 0.0;
         for (int pi = 0; pi < c.n_passes; ++pi) {
-            const BatchPass p = a.passes[c.pass_off + pi];
+            const BatchPass &p = a.passes[c.pass_off + pi];
             const int m = p.sp.L + p.sp.K;
             const uint32_t tsize = 1u << m, tvec = tsize >> V::bits;
             const uint64_t n_tiles = 1ull << (c.w - m);

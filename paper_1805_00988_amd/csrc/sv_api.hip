@@ -310,7 +310,19 @@ static void encode_controls(const TileSpec &sp, uint64_t ctrl, TileGate *r) {
     }
 }
 
-static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qset, const Gate &g) {
+// Store n complex entries (re, im interleaved, FP64) in the record in the
+// state's precision.
+static void put_matrix(TileGate &r, const double *U, int n, bool f32) {
+    if (!f32) {
+        std::memcpy(r.m, U, sizeof(double) * 2 * n);
+        return;
+    }
+    float *f = reinterpret_cast<float *>(r.m);
+    for (int i = 0; i < 2 * n; ++i) f[i] = (float)U[i];
+}
+
+static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qset, const Gate &g,
+                                  bool f32) {
     TileGate r;
     std::memset(&r, 0, sizeof(r));
     encode_controls(sp, g.ctrl, &r);
@@ -321,9 +333,10 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
         return -1;
     };
     if (is_diag1(g)) {
+        const double d[4] = {g.U[0], g.U[1], g.U[6], g.U[7]};
         r.kind = SK_DIAG;
         r.b0 = local_bit(sp, g.t[0]);
-        r.m[0] = g.U[0]; r.m[1] = g.U[1]; r.m[2] = g.U[6]; r.m[3] = g.U[7];
+        put_matrix(r, d, 2, f32);
         return r;
     }
     if (g.k == 1) {
@@ -331,7 +344,7 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
         bool real = true;
         for (int i = 0; i < 4; ++i) real = real && g.U[2 * i + 1] == 0.0;
         r.kind = is_x(g) ? SK_SWAP : (real ? SK_REAL : SK_GEN);
-        std::memcpy(r.m, g.U, sizeof(double) * 8);
+        put_matrix(r, g.U, 4, f32);
         return r;
     }
     r.kind = SK_2Q;
@@ -339,17 +352,19 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
     if (p0 < p1) {
         r.b0 = p0;
         r.b1 = p1;
-        std::memcpy(r.m, g.U, sizeof(double) * 32);
+        put_matrix(r, g.U, 16, f32);
     } else { // bit 0 of the matrix index must name the lower position: swap index bits
         r.b0 = p1;
         r.b1 = p0;
+        double u[32];
         auto sw = [](int i) { return ((i & 1) << 1) | ((i >> 1) & 1); };
         for (int row = 0; row < 4; ++row)
             for (int col = 0; col < 4; ++col) {
                 const int src = sw(row) * 4 + sw(col), dst = row * 4 + col;
-                r.m[2 * dst] = g.U[2 * src];
-                r.m[2 * dst + 1] = g.U[2 * src + 1];
+                u[2 * dst] = g.U[2 * src];
+                u[2 * dst + 1] = g.U[2 * src + 1];
             }
+        put_matrix(r, u, 16, f32);
     }
     return r;
 }
@@ -357,7 +372,8 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
 // Group the pass's gates (in order) into sweeps of at most W register
 // qubits; diagonal one-qubit gates join the current sweep whatever their
 // target, since they act per amplitude.
-static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w) {
+static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w,
+                             bool f32) {
     PassCode pc;
     pc.sp = sp;
     pc.m = sp.L + sp.K;
@@ -373,7 +389,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         sw.n_gates = (int)cur.size();
         for (int j = 0; j < kSweepW; ++j) sw.qpos[j] = j < W ? qset[j] : 0;
         pc.sweeps.push_back(sw);
-        for (const Gate *g : cur) pc.gates.push_back(encode_sweep_gate(sp, qset, *g));
+        for (const Gate *g : cur) pc.gates.push_back(encode_sweep_gate(sp, qset, *g, f32));
         cur.clear();
         qset.clear();
     };
@@ -418,7 +434,7 @@ static int tile_single(sv_state *h, const Gate &g) {
     TileSpec sp{};
     tile_layout(h->n, std::min(h->n, tile_max_qubits(h->dtype)), std::min(h->n, 6), g.tmask(), &sp);
     std::vector<const Gate *> one{&g};
-    const PassCode pc = compile_pass(sp, one, sweep_width(h->dtype));
+    const PassCode pc = compile_pass(sp, one, sweep_width(h->dtype), h->dtype == SV_C64);
     int rc = ensure_arena(h, pc.bytes());
     if (rc) return rc;
     if ((rc = stage_wait(h))) return rc;
@@ -503,7 +519,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         }
         TileSpec sp{};
         tile_layout(h->n, mmax, lmin, needed, &sp);
-        code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype));
+        code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64);
         offs[pi] = total;
         total += align256(code[pi].bytes());
     }
@@ -848,7 +864,7 @@ static BatchProgram compile_batch(const std::vector<int> &widths,
             } else {
                 tile_layout(w, m, lmin, needed, &sp);
             }
-            const PassCode pc = compile_pass(sp, ptrs, sweep_w);
+            const PassCode pc = compile_pass(sp, ptrs, sweep_w, dtype == SV_C64);
             BatchPass q{};
             q.sp = sp;
             q.n_sweeps = (int)pc.sweeps.size();

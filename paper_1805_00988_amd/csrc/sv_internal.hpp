@@ -85,7 +85,8 @@ struct TileGate {
     int32_t b0, b1;
     uint32_t cin;      // control bits inside the tile (local positions)
     uint64_t cout;     // control bits outside the tile (global positions)
-    double m[32];      // matrix entries, complex interleaved
+    double m[32];      // matrix entries, complex interleaved: FP64, or FP32 packed into
+                       // the first half of the storage for complex64 states
 };
 
 constexpr int kSweepW = 4; // tile qubits held in registers per sweep (fewer for tiny tiles)
