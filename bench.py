@@ -73,6 +73,70 @@ def cpu_baseline(n: int, circ, budget_s: float):
                       f"state in FP64 complex ({dt:.1f} s)"}
 
 
+def bench_fused(args, regs, lib, sv, _lib, torch):
+    """The same workload through the fused path: greedy blocks of up to
+    fuse-k qubits in tile passes (matrix cores for complex64, FP64 vector
+    ALUs for complex128).  Fidelity is taken against the plain path's final
+    state of the same register."""
+    prec_c64 = sv.SV_PREC_SPLIT_BF16 if args.fused_prec == "bf16x3" else sv.SV_PREC_FP32
+    plain_final = {}
+    for r in regs:  # reference: plain final state of this step's input
+        plain_final[r["n"]] = r["state"].amps.clone()
+    nb = ctypes.c_int()
+    norm = ctypes.c_double()
+
+    def fstep():
+        for r in regs:
+            h = r["state"].handle
+            prec = prec_c64 if r["dtype"] == "c64" else sv.SV_PREC_NATIVE
+            _lib.check(lib.sv_set_basis(h, r["qft"].basis))
+            blocks = 0
+            for key, c in (("ops_qft", r["qft"]), ("ops_rnd", r["rnd"])):
+                _lib.check(lib.sv_run_fused(h, sv._opptr(r[key]), len(c.gates), None, 0, args.fuse_k, prec,
+                                            ctypes.byref(nb)))
+                blocks += nb.value
+            _lib.check(lib.sv_probabilities(h, ctypes.c_void_p(r["probs"].data_ptr()), ctypes.byref(norm)))
+            r["fused_blocks"], r["fused_norm"] = blocks, norm.value
+
+    fstep()
+    for r in regs:
+        _lib.check(lib.sv_timing(r["state"].handle, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        fstep()
+        print(f"# fused step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"prec_complex64": args.fused_prec, "prec_complex128": "fp64 vector", "k_max": args.fuse_k,
+           "ms_per_step": dt / args.steps * 1e3, "registers": {}}
+    total = 0
+    for r in regs:
+        per = read_stats(lib, r["state"].handle)
+        _lib.check(lib.sv_timing(r["state"].handle, 0))
+        a = r["state"].amps
+        b = plain_final[r["n"]]
+        ov, na, nb2 = 0j, 0.0, 0.0
+        for c0 in range(0, a.numel(), 1 << 28):  # BLAS dot takes < 2^31 elements
+            ac, bc = a[c0:c0 + (1 << 28)], b[c0:c0 + (1 << 28)]
+            ov += complex(torch.vdot(bc, ac).item())
+            na += float(torch.vdot(ac, ac).real.item())
+            nb2 += float(torch.vdot(bc, bc).real.item())
+        fid = abs(ov) ** 2 / (na * nb2)
+        total += r["updates"]
+        fk = per.get("fused_block", (1, 0.0, 0.0))
+        out["registers"][f"{r['n']}q_{r['dtype']}"] = {
+            "blocks_per_step": r["fused_blocks"], "norm": r["fused_norm"],
+            "fidelity_vs_plain": fid,
+            "fused_pass_launches": fk[0] // args.steps,
+            "fused_pass_ms_per_step": round(fk[1] / args.steps, 3),
+            "fused_pass_GBps": round(fk[2] / (fk[1] * 1e-3) / 1e9, 1) if fk[1] > 0 else None}
+        del b
+    out["value"] = total * args.steps / dt
+    out["unit"] = "updates/s"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +148,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-qubits", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--fuse-k", type=int, default=5)
+    ap.add_argument("--fused-prec", default="bf16x3", choices=["fp32", "bf16x3"],
+                    help="matrix-core arithmetic of complex64 fused blocks")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -183,6 +251,10 @@ def main():
             "norm": r["norm"], "z0": r["z0"],
         }
 
+    fused = None
+    if not args.no_fused:
+        fused = bench_fused(args, regs, lib, sv, _lib, torch)
+
     cpu = None
     if not args.no_cpu:
         n_cpu = args.cpu_qubits
@@ -210,6 +282,7 @@ def main():
         "hbm_roofline_frac_effective": round(total_plain_bytes / elapsed / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fused": fused,
         "breakdown": breakdown,
     }
     print(json.dumps(out), flush=True)

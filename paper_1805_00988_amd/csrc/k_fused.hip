@@ -95,49 +95,46 @@ __device__ __forceinline__ void stage_out(typename V16<T>::type *v, const cpx<T>
     }
 }
 
-// Positions of a block inside the tile: the block's qubits (bit j of the
-// matrix index) and the remaining tile bits (group index).
-struct BlockPos {
-    int k;
-    int qpos[6];
-    int gpos[16];
-    int ng;
-};
-
 // ------------------------------------------------- native (vector ALU)
 // One thread per group: the 2^K amplitudes go to registers, every output is
 // a dot product with a row of U (uniform across the wave, read through the
-// scalar cache), written back to the group's own LDS slots.
+// scalar cache), written back to the group's own LDS slots.  The blocks of a
+// pass are applied one after another to the staged tile.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_dense_native(typename V16<T>::type *v, TileSpec sp, int m,
-                                                      BlockPos bp, const cpx<T> *__restrict__ U,
+                                                      const DenseBlock *__restrict__ blocks, int n_blocks,
+                                                      const char *__restrict__ base_ptr,
                                                       uint64_t n_tiles) {
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
     constexpr int D = 1 << K;
     const uint32_t tsize = 1u << m;
     const uint32_t n_groups = tsize >> K;
-    uint32_t F[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) F[j] = deposit((uint32_t)j, bp.qpos, K);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
         stage_in<T>(v, lds, sp, base, tsize);
         __syncthreads();
-        for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
-            const uint32_t gb = deposit(g, bp.gpos, bp.ng);
-            cpx<T> x[D];
+        for (int b = 0; b < n_blocks; ++b) {
+            const DenseBlock &B = blocks[b];
+            const cpx<T> *U = reinterpret_cast<const cpx<T> *>(base_ptr + B.op_off);
+            uint32_t F[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) x[j] = lds[gb | F[j]];
+            for (int j = 0; j < D; ++j) F[j] = deposit((uint32_t)j, B.bp.qpos, K);
+            for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
+                const uint32_t gb = deposit(g, B.bp.gpos, B.bp.ng);
+                cpx<T> x[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                cpx<T> acc = cmul(U[i * D], x[0]);
+                for (int j = 0; j < D; ++j) x[j] = lds[gb | F[j]];
 #pragma unroll
-                for (int j = 1; j < D; ++j) acc = cfma(U[i * D + j], x[j], acc);
-                lds[gb | F[i]] = acc;
+                for (int i = 0; i < D; ++i) {
+                    cpx<T> acc = cmul(U[i * D], x[0]);
+#pragma unroll
+                    for (int j = 1; j < D; ++j) acc = cfma(U[i * D + j], x[j], acc);
+                    lds[gb | F[i]] = acc;
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
         stage_out<T>(v, lds, sp, base, tsize);
         __syncthreads();
     }
@@ -176,8 +173,9 @@ __device__ __forceinline__ __bf16 bf16_hi(float x) { return (__bf16)x; }
 __device__ __forceinline__ __bf16 bf16_lo(float x, __bf16 hi) { return (__bf16)(x - (float)hi); }
 
 template <int K, int PREC>
-__global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec sp, int m, BlockPos bp,
-                                                             const void *__restrict__ frag,
+__global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec sp, int m,
+                                                             const DenseBlock *__restrict__ blocks,
+                                                             int n_blocks, const char *__restrict__ base_ptr,
                                                              uint64_t n_tiles) {
     using S = MfmaShape<K, PREC>;
     constexpr int D = 1 << K;         // amplitudes per group = output columns
@@ -195,31 +193,34 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
     const int r = lane % ROWS;          // A row (group within wave-tile) / D column (output amp)
     const int kk = lane / ROWS;         // K sub-index of the lane
 
-    // B fragments in registers for the whole launch
-    float bf32[2][PREC == 1 ? KS : 1];
-    bf16x8 bbf[2][PREC == 2 ? KS : 1][2];
-    if constexpr (PREC == 1) {
-        const float *f = reinterpret_cast<const float *>(frag);
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int s = 0; s < KS; ++s) bf32[p][s] = f[(p * KS + s) * 64 + lane];
-    } else {
-        const bf16x8 *f = reinterpret_cast<const bf16x8 *>(frag);
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-#pragma unroll
-                for (int hl = 0; hl < 2; ++hl) bbf[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
-    }
-    const uint32_t Fcol = deposit((uint32_t)r, bp.qpos, K); // this lane's output amplitude
-    const uint32_t Grow = deposit((uint32_t)r, bp.gpos, bp.ng);
-
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
         stage_in<float>(v, lds, sp, base, tsize);
         __syncthreads();
+        for (int b = 0; b < n_blocks; ++b) {
+        const DenseBlock &B = blocks[b];
+        const BlockPos &bp = B.bp;
+        const void *frag = base_ptr + B.op_off;
+        // this block's B fragments in registers (the same for every group)
+        float bf32[2][PREC == 1 ? KS : 1];
+        bf16x8 bbf[2][PREC == 2 ? KS : 1][2];
+        if constexpr (PREC == 1) {
+            const float *f = reinterpret_cast<const float *>(frag);
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int s = 0; s < KS; ++s) bf32[p][s] = f[(p * KS + s) * 64 + lane];
+        } else {
+            const bf16x8 *f = reinterpret_cast<const bf16x8 *>(frag);
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+#pragma unroll
+                    for (int hl = 0; hl < 2; ++hl) bbf[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
+        }
+        const uint32_t Fcol = deposit((uint32_t)r, bp.qpos, K); // this lane's output amplitude
+        const uint32_t Grow = deposit((uint32_t)r, bp.gpos, bp.ng);
         for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
             const uint32_t gw = deposit(wt * ROWS, bp.gpos, bp.ng);
             const uint32_t arow = gw | Grow;
@@ -301,6 +302,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
             }
         }
         __syncthreads();
+        } // blocks
         stage_out<float>(v, lds, sp, base, tsize);
         __syncthreads();
     }
@@ -308,34 +310,13 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
 }
 
 // ---------------------------------------------------------------- launch
-static BlockPos block_positions(const TileSpec &sp, int m, int k, const int *qubits) {
-    BlockPos bp{};
-    bp.k = k;
-    uint32_t used = 0;
-    for (int j = 0; j < k; ++j) {
-        const int q = qubits[j];
-        int lb = -1;
-        if (q < sp.L) lb = q;
-        for (int i = 0; i < sp.K; ++i)
-            if (sp.high[i] == q) lb = sp.L + i;
-        bp.qpos[j] = lb;
-        used |= 1u << lb;
-    }
-    bp.ng = 0;
-    for (int b = 0; b < m; ++b)
-        if (!((used >> b) & 1u)) bp.gpos[bp.ng++] = b;
-    return bp;
-}
-
 int fused_tile_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
 
-hipError_t launch_dense(void *amps, int n, int dtype, const TileSpec &sp, int k, const int *qubits,
-                        const void *dev_mat, int prec, hipStream_t s) {
+hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, int k,
+                             const DenseBlock *dev_blocks, int n_blocks, const char *dev_base, int prec,
+                             hipStream_t s) {
     const int m = sp.L + sp.K;
-    if (m > n || k > m || k < 1 || k > 5) return hipErrorInvalidValue;
-    const BlockPos bp = block_positions(sp, m, k, qubits);
-    for (int j = 0; j < k; ++j)
-        if (bp.qpos[j] < 0) return hipErrorInvalidValue;
+    if (m > n || k > m || k < 1 || k > 5 || n_blocks < 1) return hipErrorInvalidValue;
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1024);
@@ -347,8 +328,8 @@ hipError_t launch_dense(void *amps, int n, int dtype, const TileSpec &sp, int k,
     if (k == KK && prec == PP) {                                                                   \
         (void)hipFuncSetAttribute((const void *)k_dense_mfma<KK, PP>,                              \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
-        k_dense_mfma<KK, PP><<<grid, kFuseThreads, lds, s>>>((float4 *)amps, sp, m, bp, dev_mat,   \
-                                                             n_tiles);                             \
+        k_dense_mfma<KK, PP><<<grid, kFuseThreads, lds, s>>>((float4 *)amps, sp, m, dev_blocks,    \
+                                                             n_blocks, dev_base, n_tiles);         \
         return hipGetLastError();                                                                  \
     }
         SV_MFMA_CASE(5, 1)
@@ -362,8 +343,8 @@ hipError_t launch_dense(void *amps, int n, int dtype, const TileSpec &sp, int k,
     if (k == KK) {                                                                                 \
         (void)hipFuncSetAttribute((const void *)k_dense_native<TT, KK>,                            \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
-        k_dense_native<TT, KK><<<grid, 256, lds, s>>>((VT *)amps, sp, m, bp,                       \
-                                                      (const cpx<TT> *)dev_mat, n_tiles);          \
+        k_dense_native<TT, KK><<<grid, 256, lds, s>>>((VT *)amps, sp, m, dev_blocks, n_blocks,      \
+                                                      dev_base, n_tiles);                          \
         return hipGetLastError();                                                                  \
     }
     if (dtype == SV_C64) {

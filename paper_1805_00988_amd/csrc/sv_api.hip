@@ -448,25 +448,25 @@ static int tile_single(sv_state *h, const Gate &g) {
 // gate left behind, and its targets fit in the tile (low block plus at most
 // kmax further qubits).  Gates left behind block their qubits for the rest
 // of the scan, so every pair of gates sharing a qubit keeps its order.
-static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, int lmin) {
+static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
+                                        int mmax, int lmin) {
     std::vector<Pass> passes;
-    std::vector<char> done(gs.size(), 0);
+    std::vector<char> done(tm.size(), 0);
     size_t first = 0;
     const uint64_t low = lmin >= 64 ? ~0ull : ((1ull << lmin) - 1ull);
     const int kmax = std::max(0, mmax - lmin);
-    while (first < gs.size()) {
+    while (first < tm.size()) {
         Pass p;
         p.S = low;
         uint64_t blocked = 0;
         int used = 0;
-        for (size_t i = first; i < gs.size(); ++i) {
+        for (size_t i = first; i < tm.size(); ++i) {
             if (done[i]) continue;
-            const Gate &g = gs[i];
-            if (g.qmask() & blocked) {
-                blocked |= g.qmask();
+            if (qm[i] & blocked) {
+                blocked |= qm[i];
                 continue;
             }
-            const uint64_t need = g.tmask() & ~p.S;
+            const uint64_t need = tm[i] & ~p.S;
             const int nn = __builtin_popcountll(need);
             if (used + nn <= kmax) {
                 p.S |= need;
@@ -474,14 +474,23 @@ static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, 
                 p.gates.push_back((int)i);
                 done[i] = 1;
             } else {
-                blocked |= g.qmask();
+                blocked |= qm[i];
             }
         }
         passes.push_back(std::move(p));
-        while (first < gs.size() && done[first]) ++first;
+        while (first < tm.size() && done[first]) ++first;
     }
-    (void)n;
     return passes;
+}
+
+static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, int lmin) {
+    (void)n;
+    std::vector<uint64_t> tm(gs.size()), qm(gs.size());
+    for (size_t i = 0; i < gs.size(); ++i) {
+        tm[i] = gs[i].tmask();
+        qm[i] = gs[i].qmask();
+    }
+    return schedule_masks(tm, qm, mmax, lmin);
 }
 
 // A single gate that the streamed kernels cannot take: a two-qubit gate with
@@ -701,61 +710,139 @@ static bool mfma_ok(const sv_state *h, int k, int prec) {
     return m >= k && ((1u << m) >> k) % rows == 0;
 }
 
-// Bytes a block needs in the arena (matrix in the state's precision, or the
-// MFMA fragments).
-static size_t block_stage_bytes(const sv_state *h, int k, bool mfma, int prec) {
-    if (mfma) return align256(frag_bytes(k, prec));
-    const size_t el = h->dtype == SV_C64 ? 8 : 16;
-    return align256(((size_t)1 << (2 * k)) * el);
-}
-
-static void stage_block(sv_state *h, const std::complex<double> *U, int k, bool mfma, int prec,
-                        size_t off) {
-    char *dst = h->h_arena + off;
-    if (mfma) {
-        make_fragments(U, k, prec, dst);
-        return;
-    }
-    const int n = 1 << (2 * k);
-    if (h->dtype == SV_C64) {
-        float *f = reinterpret_cast<float *>(dst);
-        for (int i = 0; i < n; ++i) {
-            f[2 * i] = (float)U[i].real();
-            f[2 * i + 1] = (float)U[i].imag();
-        }
-    } else {
-        double *d = reinterpret_cast<double *>(dst);
-        for (int i = 0; i < n; ++i) {
-            d[2 * i] = U[i].real();
-            d[2 * i + 1] = U[i].imag();
-        }
-    }
-}
-
-static int launch_block(sv_state *h, int k, const int *qubits, bool mfma, int prec, size_t off) {
-    uint64_t needed = 0;
-    for (int j = 0; j < k; ++j) needed |= 1ull << qubits[j];
+// A fused tile pass: the tile layout, the uniform block width k of its
+// blocks (narrower blocks are padded with identity qubits), whether it runs
+// on the matrix cores, and its blocks' positions and padded matrices.
+struct FusedPass {
     TileSpec sp{};
+    int m = 0;
+    int k = 0;
+    bool mfma = false;
+    std::vector<DenseBlock> blocks;
+    std::vector<std::vector<std::complex<double>>> mats;
+};
+
+static size_t dense_op_bytes(const sv_state *h, int k, bool mfma, int prec) {
+    if (mfma) return align256(frag_bytes(k, prec));
+    return align256(((size_t)1 << (2 * k)) * (h->dtype == SV_C64 ? 8 : 16));
+}
+
+static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp, int prec) {
+    return align256(fp.blocks.size() * sizeof(DenseBlock)) +
+           fp.blocks.size() * dense_op_bytes(h, fp.k, fp.mfma, prec);
+}
+
+// Embed a k-qubit matrix in K qubits (extra index bits k..K-1 act as identity).
+static std::vector<std::complex<double>> pad_matrix(const std::vector<std::complex<double>> &M, int k, int K) {
+    const int d = 1 << k, D = 1 << K;
+    std::vector<std::complex<double>> P((size_t)D * D, 0.0);
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c)
+            if ((r >> k) == (c >> k)) P[(size_t)r * D + c] = M[(size_t)(r & (d - 1)) * d + (c & (d - 1))];
+    return P;
+}
+
+// Build the passes for a list of blocks (each: qubits q[0..k-1], matrix M).
+static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector<Block> &bs, int prec) {
     const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
-    tile_layout(h->n, mmax, std::min(h->n, h->dtype == SV_C64 ? 7 : 6), needed, &sp);
+    const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
+    std::vector<uint64_t> tm(bs.size());
+    for (size_t b = 0; b < bs.size(); ++b) {
+        tm[b] = 0;
+        for (int j = 0; j < bs[b].k; ++j) tm[b] |= 1ull << bs[b].q[j];
+    }
+    std::vector<Pass> passes = schedule_masks(tm, tm, mmax, lmin);
+    std::vector<FusedPass> out;
+    for (const Pass &p : passes) {
+        FusedPass fp;
+        uint64_t needed = 0;
+        int kmax = 0;
+        for (int bi : p.gates) {
+            needed |= tm[bi];
+            kmax = std::max(kmax, bs[bi].k);
+        }
+        tile_layout(h->n, mmax, lmin, needed, &fp.sp);
+        fp.m = fp.sp.L + fp.sp.K;
+        fp.mfma = prec != SV_PREC_NATIVE && mfma_ok(h, std::max(4, kmax), prec);
+        fp.k = fp.mfma ? std::max(4, kmax) : kmax;
+        for (int bi : p.gates) {
+            const Block &B = bs[bi];
+            DenseBlock db{};
+            db.bp.k = fp.k;
+            uint32_t used = 0;
+            for (int j = 0; j < B.k; ++j) {
+                db.bp.qpos[j] = local_bit(fp.sp, B.q[j]);
+                used |= 1u << db.bp.qpos[j];
+            }
+            // padding qubits: the highest tile positions the block does not use
+            for (int j = B.k, pos = fp.m - 1; j < fp.k; ++j) {
+                while ((used >> pos) & 1u) --pos;
+                db.bp.qpos[j] = pos;
+                used |= 1u << pos;
+            }
+            db.bp.ng = 0;
+            for (int b = 0; b < fp.m; ++b)
+                if (!((used >> b) & 1u)) db.bp.gpos[db.bp.ng++] = b;
+            fp.blocks.push_back(db);
+            fp.mats.push_back(B.k == fp.k ? B.M : pad_matrix(B.M, B.k, fp.k));
+        }
+        out.push_back(std::move(fp));
+    }
+    return out;
+}
+
+// Write a fused pass (block records, then one operand per block) at 'off';
+// operand offsets are relative to the arena base.
+static void stage_fused(sv_state *h, FusedPass &fp, int prec, size_t off) {
+    const size_t ob = dense_op_bytes(h, fp.k, fp.mfma, prec);
+    size_t opo = off + align256(fp.blocks.size() * sizeof(DenseBlock));
+    for (size_t b = 0; b < fp.blocks.size(); ++b, opo += ob) {
+        fp.blocks[b].op_off = (int64_t)opo;
+        char *dst = h->h_arena + opo;
+        const std::complex<double> *U = fp.mats[b].data();
+        if (fp.mfma) {
+            make_fragments(U, fp.k, prec, dst);
+        } else if (h->dtype == SV_C64) {
+            float *f = reinterpret_cast<float *>(dst);
+            for (size_t i = 0; i < fp.mats[b].size(); ++i) {
+                f[2 * i] = (float)U[i].real();
+                f[2 * i + 1] = (float)U[i].imag();
+            }
+        } else {
+            double *d = reinterpret_cast<double *>(dst);
+            for (size_t i = 0; i < fp.mats[b].size(); ++i) {
+                d[2 * i] = U[i].real();
+                d[2 * i + 1] = U[i].imag();
+            }
+        }
+    }
+    std::memcpy(h->h_arena + off, fp.blocks.data(), fp.blocks.size() * sizeof(DenseBlock));
+}
+
+static int launch_fused(sv_state *h, const FusedPass &fp, int prec, size_t off) {
     Timed tm(h, K_FUSED, 2.0 * state_bytes(h));
-    SV_HIP(launch_dense(h->amps, h->n, h->dtype, sp, k, qubits, h->d_arena + off,
-                        mfma ? prec : SV_PREC_NATIVE, h->stream));
+    SV_HIP(launch_dense_pass(h->amps, h->n, h->dtype, fp.sp, fp.k,
+                             reinterpret_cast<const DenseBlock *>(h->d_arena + off), (int)fp.blocks.size(),
+                             h->d_arena, fp.mfma ? prec : SV_PREC_NATIVE, h->stream));
     return SV_OK;
 }
 
-// Gate of a 1- or 2-qubit block, for the streamed kernels.
-static Gate block_gate(const Block &b) {
-    Gate g{};
-    g.k = b.k;
-    g.t[0] = b.q[0];
-    g.t[1] = b.k == 2 ? b.q[1] : -1;
-    g.ctrl = 0;
-    for (int i = 0; i < (1 << (2 * b.k)); ++i) {
-        g.U[2 * i] = b.M[i].real();
-        g.U[2 * i + 1] = b.M[i].imag();
+// Stage, upload and launch a sequence of fused passes.
+static int run_fused_passes(sv_state *h, std::vector<FusedPass> &fps, int prec) {
+    std::vector<size_t> offs(fps.size());
+    size_t total = 0;
+    for (size_t i = 0; i < fps.size(); ++i) {
+        offs[i] = total;
+        total += align256(fused_pass_bytes(h, fps[i], prec));
     }
-    return g;
+    int rc = ensure_arena(h, total);
+    if (rc) return rc;
+    if ((rc = stage_wait(h))) return rc;
+    for (size_t i = 0; i < fps.size(); ++i) stage_fused(h, fps[i], prec, offs[i]);
+    if ((rc = upload_arena(h, total))) return rc;
+    for (size_t i = 0; i < fps.size(); ++i)
+        if ((rc = launch_fused(h, fps[i], prec, offs[i]))) return rc;
+    return SV_OK;
 }
 
 static int parse_ops(const sv_state *h, int n, const sv_op *ops, int n_ops, const double *params,
@@ -1216,16 +1303,13 @@ int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int p
         if (!std::isfinite(U[i])) return fail(SV_EINVAL, "matrix entry is not finite");
     if (prec != SV_PREC_NATIVE && (h->dtype != SV_C64 || k < 4))
         return fail(SV_EUNSUPPORTED, "matrix-core blocks need a complex64 state and k >= 4");
-    std::vector<std::complex<double>> M((size_t)D * D);
-    for (int i = 0; i < D * D; ++i) M[i] = {U[2 * i], U[2 * i + 1]};
-    const bool mfma = mfma_ok(h, k, prec);
-    const size_t bytes = block_stage_bytes(h, k, mfma, prec);
-    int rc = ensure_arena(h, bytes);
-    if (rc) return rc;
-    if ((rc = stage_wait(h))) return rc;
-    stage_block(h, M.data(), k, mfma, prec, 0);
-    if ((rc = upload_arena(h, bytes))) return rc;
-    return launch_block(h, k, qubits, mfma, prec, 0);
+    Block B;
+    B.k = k;
+    for (int j = 0; j < k; ++j) B.q[j] = qubits[j];
+    B.M.resize((size_t)D * D);
+    for (int i = 0; i < D * D; ++i) B.M[i] = {U[2 * i], U[2 * i + 1]};
+    std::vector<FusedPass> fps = compile_fused(h, std::vector<Block>{B}, prec);
+    return run_fused_passes(h, fps, prec);
 }
 
 int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int n_params,
@@ -1273,35 +1357,8 @@ int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params,
         if (__builtin_popcountll(g.qmask()) > kk)
             return fail(SV_EINVAL, "a gate touches more qubits than k_max");
     std::vector<Block> bs = fuse(gs, kk);
-    // stage every dense block once, then launch in order
-    std::vector<size_t> offs(bs.size(), 0);
-    std::vector<char> mf(bs.size(), 0);
-    size_t total = 0;
-    // 1- and 2-qubit blocks use the streamed kernels, except two-qubit blocks
-    // with a target inside a complex64 vector, which take the dense path
-    std::vector<char> streamed(bs.size(), 0);
-    for (size_t b = 0; b < bs.size(); ++b)
-        streamed[b] = bs[b].k <= 2 && !needs_tile(h, block_gate(bs[b]));
-    for (size_t b = 0; b < bs.size(); ++b) {
-        if (streamed[b]) continue;
-        mf[b] = mfma_ok(h, bs[b].k, prec);
-        offs[b] = total;
-        total += block_stage_bytes(h, bs[b].k, mf[b], prec);
-    }
-    if (total) {
-        if ((rc = ensure_arena(h, total))) return rc;
-        if ((rc = stage_wait(h))) return rc;
-        for (size_t b = 0; b < bs.size(); ++b)
-            if (!streamed[b]) stage_block(h, bs[b].M.data(), bs[b].k, mf[b], prec, offs[b]);
-        if ((rc = upload_arena(h, total))) return rc;
-    }
-    for (size_t b = 0; b < bs.size(); ++b) {
-        if (streamed[b]) {
-            if ((rc = apply_one(h, block_gate(bs[b])))) return rc;
-        } else if ((rc = launch_block(h, bs[b].k, bs[b].q, mf[b], prec, offs[b]))) {
-            return rc;
-        }
-    }
+    std::vector<FusedPass> fps = compile_fused(h, bs, prec);
+    if ((rc = run_fused_passes(h, fps, prec))) return rc;
     if (n_blocks_out) *n_blocks_out = (int)bs.size();
     return SV_OK;
 }

@@ -120,8 +120,24 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
                        int n_sweeps, const TileGate *dev_gates, hipStream_t s);
 int tile_max_qubits(int dtype);
 int sweep_width(int dtype);
-hipError_t launch_dense(void *amps, int n, int dtype, const TileSpec &sp, int k, const int *qubits,
-                        const void *dev_mat, int prec, hipStream_t s);
+// Dense blocks of a fused tile pass: positions of the block's qubits in the
+// tile (bit j of the matrix index <-> qpos[j]) and of the remaining tile bits
+// (group index), and the byte offset of the block's operand (the matrix in
+// the state's precision, or MFMA operand fragments) from the pass's base.
+struct BlockPos {
+    int k;
+    int qpos[6];
+    int gpos[16];
+    int ng;
+};
+struct DenseBlock {
+    BlockPos bp;
+    int32_t pad;
+    int64_t op_off;
+};
+hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, int k,
+                             const DenseBlock *dev_blocks, int n_blocks, const char *dev_base, int prec,
+                             hipStream_t s);
 int fused_tile_qubits(int dtype);
 
 hipError_t launch_probabilities(const void *amps, int n, int dtype, void *dev_out,
