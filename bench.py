@@ -137,6 +137,85 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
     return out
 
 
+def timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn()
+        print(f"# step {i + 1}/{steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def other_workload(args):
+    """Fusion (30 qubits, depth 40, complex64, fused at k = 4 and 5), batch
+    (4096 ladder-ansatz circuits of 10..20 qubits, one graph launch) or
+    adjoint (24-qubit ansatz, 576 parameters, loss and full gradient)."""
+    import torch
+
+    import circuits as C
+    import paper_1805_00988_amd as sv
+    from paper_1805_00988_amd import _lib
+
+    lib = _lib.load()
+    torch.cuda.set_device(0)
+    out = {"metric": "gate-amplitude updates/s", "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "data": "synthetic", "vs_baseline": None}
+    if args.workload == "fusion":
+        circ = C.config2(n=30, seed=args.seed, depth=40)
+        st = sv.State(30, "c64")
+        ops = sv.ops_from_gates(circ.gates)
+        res = {}
+        nb = ctypes.c_int()
+        for label, fn in [("plain", lambda: lib.sv_run(st.handle, sv._opptr(ops), len(circ), None, 0,
+                                                       sv.SV_RUN_TILED)),
+                          ("fused_k4_fp32", lambda: lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ), None,
+                                                                     0, 4, sv.SV_PREC_FP32, ctypes.byref(nb))),
+                          ("fused_k5_fp32", lambda: lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ), None,
+                                                                     0, 5, sv.SV_PREC_FP32, ctypes.byref(nb))),
+                          ("fused_k5_bf16x3", lambda: lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ),
+                                                                       None, 0, 5, sv.SV_PREC_SPLIT_BF16,
+                                                                       ctypes.byref(nb)))]:
+            def step():
+                _lib.check(lib.sv_set_basis(st.handle, 0))
+                _lib.check(fn())
+            for _ in range(args.warmup):
+                step()
+            dt = timed(step, args.steps, torch)
+            res[label] = {"updates_per_s": circ.updates() * args.steps / dt,
+                          "ms_per_step": dt / args.steps * 1e3,
+                          "blocks": nb.value if label != "plain" else None}
+        out.update({"value": res["fused_k5_bf16x3"]["updates_per_s"], "dtype": "f32",
+                    "config": {"workload": "30-qubit random circuit, depth 40 (1q layer + 15 CZ), complex64"},
+                    "variants": res})
+    elif args.workload == "batch":
+        circs = [c.bound() for c in C.config3(seed=args.seed)]
+        b = sv.Batch(circs, "c64", z_mask=1)
+        for _ in range(max(1, args.warmup)):
+            b.run()
+        dt = timed(lambda: b.run(), args.steps, torch)
+        ups = sum(c.updates() for c in circs)
+        tuned = b.tune(reps=2)
+        dt2 = timed(lambda: b.run(), args.steps, torch)
+        out.update({"value": ups * args.steps / dt2, "dtype": "f32",
+                    "config": {"workload": "4096 ladder-ansatz circuits, widths 10..20, 8 layers, complex64, "
+                                           "one graph launch, <Z_0> per circuit"},
+                    "ms_per_step_default": dt / args.steps * 1e3, "ms_per_step_tuned": dt2 / args.steps * 1e3,
+                    "tuned": tuned})
+    else:
+        from paper_1805_00988_amd.autograd import ExpectationCircuit
+        circ, masks, coeffs = C.config4(seed=args.seed)
+        ec = ExpectationCircuit(circ.n, circ.gates, masks, coeffs, "c128")
+        for _ in range(max(1, args.warmup)):
+            ec.loss_and_grad(circ.params)
+        dt = timed(lambda: ec.loss_and_grad(circ.params), args.steps, torch)
+        out.update({"value": circ.updates() * args.steps / dt, "dtype": "f64",
+                    "config": {"workload": "24-qubit ansatz, 12 layers RY/RZ + CNOT ring, complex128, "
+                                           "loss + 576-parameter adjoint gradient (forward included)"},
+                    "ms_per_step": dt / args.steps * 1e3})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +231,10 @@ def main():
     ap.add_argument("--fuse-k", type=int, default=5)
     ap.add_argument("--fused-prec", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="matrix-core arithmetic of complex64 fused blocks")
+    ap.add_argument("--workload", default="plain-at-scale",
+                    choices=["plain-at-scale", "fusion", "batch", "adjoint"],
+                    help="plain-at-scale (default headline line); the others time the "
+                         "fusion, batched and adjoint workloads on their own")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -159,6 +242,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding of the "
                           "state vector is a design note, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload != "plain-at-scale":
+        print(json.dumps(other_workload(args)), flush=True)
+        return
 
     import torch
 

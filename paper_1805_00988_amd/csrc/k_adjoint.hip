@@ -1,14 +1,15 @@
 // Adjoint-method gradient kernels.
 //
 // With psi the circuit output and lam = H psi for a diagonal observable H,
-// the reverse sweep undoes one gate at a time on both vectors.  For a
+// the reverse sweep undoes the gates, last first, on both vectors.  For a
 // parametrised gate U(theta) whose derivative is U' = c M U (c a constant,
 // M a 2x2 "probe": the Pauli of a rotation, or the projector |1><1| of the
 // phase gate) the gradient term 2 Re <lam| U' |psi_before> equals a real
 // multiple of Im <lam| M |psi_after>, evaluated on the vectors before the
-// gate is undone.  One kernel does the probe and the undo in the same pass
-// over both vectors; the probe's FP64 partial sums go to one slot per gate.
+// gate is undone.  The sweep runs as tile passes over both vectors staged in
+// LDS; each probe's FP64 partial sums go to one slot per gate.
 #include "sv_internal.hpp"
+#include "tile_sweep.hpp"
 
 #include <algorithm>
 
@@ -95,69 +96,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_init(const typename AV<
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// Probe then undo one (controlled) one-qubit gate on psi and lam.
-template <typename T>
-__global__ __launch_bounds__(kAdjThreads) void k_adjoint_param(typename AV<T>::type *psi,
-                                                               typename AV<T>::type *lam, Enum e, int te,
-                                                               uint64_t count, Mat2<T> udag,
-                                                               Mat2<T> probe, uint32_t lane_ctrl,
-                                                               double *partials) {
-    using V = AV<T>;
-    double acc = 0.0;
-    const uint64_t bstep = 1ull << te;
-    const uint64_t stride = (uint64_t)gridDim.x * kAdjThreads;
-    for (uint64_t j = (uint64_t)blockIdx.x * kAdjThreads + threadIdx.x; j < count; j += stride) {
-        const uint64_t a = expand(e, j);
-        if ((a & e.check) != e.check) continue;
-        typename V::type pa = psi[a], pb = psi[a + bstep], la = lam[a], lb = lam[a + bstep];
-#pragma unroll
-        for (int k = 0; k < V::amps; ++k) {
-            if (((uint32_t)k & lane_ctrl) != lane_ctrl) continue;
-            const cpx<T> x0 = V::get(pa, k), x1 = V::get(pb, k);
-            const cpx<T> y0 = V::get(la, k), y1 = V::get(lb, k);
-            const cpx<T> z0 = cfma(probe.m[0], x0, cmul(probe.m[1], x1));
-            const cpx<T> z1 = cfma(probe.m[2], x0, cmul(probe.m[3], x1));
-            acc += im_conj_mul(y0, z0) + im_conj_mul(y1, z1);
-            V::put(pa, k, cfma(udag.m[0], x0, cmul(udag.m[1], x1)));
-            V::put(pb, k, cfma(udag.m[2], x0, cmul(udag.m[3], x1)));
-            V::put(la, k, cfma(udag.m[0], y0, cmul(udag.m[1], y1)));
-            V::put(lb, k, cfma(udag.m[2], y0, cmul(udag.m[3], y1)));
-        }
-        psi[a] = pa;
-        psi[a + bstep] = pb;
-        lam[a] = la;
-        lam[a + bstep] = lb;
-    }
-    acc = block_sum_d(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
-}
-
-// complex64 probe/undo on qubit 0 (pair inside one float4)
-__global__ __launch_bounds__(kAdjThreads) void k_adjoint_param_q0(float4 *psi, float4 *lam, Enum e,
-                                                                  uint64_t count, Mat2<float> udag,
-                                                                  Mat2<float> probe,
-                                                                  double *partials) {
-    double acc = 0.0;
-    const uint64_t stride = (uint64_t)gridDim.x * kAdjThreads;
-    for (uint64_t j = (uint64_t)blockIdx.x * kAdjThreads + threadIdx.x; j < count; j += stride) {
-        const uint64_t a = expand(e, j);
-        if ((a & e.check) != e.check) continue;
-        const float4 p = psi[a], l = lam[a];
-        const cpx<float> x0{p.x, p.y}, x1{p.z, p.w}, y0{l.x, l.y}, y1{l.z, l.w};
-        const cpx<float> z0 = cfma(probe.m[0], x0, cmul(probe.m[1], x1));
-        const cpx<float> z1 = cfma(probe.m[2], x0, cmul(probe.m[3], x1));
-        acc += im_conj_mul(y0, z0) + im_conj_mul(y1, z1);
-        const cpx<float> u0 = cfma(udag.m[0], x0, cmul(udag.m[1], x1));
-        const cpx<float> u1 = cfma(udag.m[2], x0, cmul(udag.m[3], x1));
-        const cpx<float> v0 = cfma(udag.m[0], y0, cmul(udag.m[1], y1));
-        const cpx<float> v1 = cfma(udag.m[2], y0, cmul(udag.m[3], y1));
-        psi[a] = float4{u0.re, u0.im, u1.re, u1.im};
-        lam[a] = float4{v0.re, v0.im, v1.re, v1.im};
-    }
-    acc = block_sum_d(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
-}
-
 // Sum each slot's partials: out[s] = sum_b partials[s * n_blocks + b].
 __global__ __launch_bounds__(kAdjThreads) void k_sum_slots(const double *partials, int n_blocks,
                                                            double *out) {
@@ -191,70 +129,191 @@ hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int
     return hipGetLastError();
 }
 
-static Enum adj_enum(int vbits, int te, bool with_target, uint64_t ctrl, uint32_t *lane_ctrl, int *np) {
-    Enum e{};
-    int pos[64];
-    int cnt = 0;
-    if (with_target) pos[cnt++] = te;
-    *lane_ctrl = (uint32_t)(ctrl & ((1ull << vbits) - 1ull));
-    uint64_t ec = ctrl >> vbits;
-    while (ec) {
-        const int b = __builtin_ctzll(ec);
-        ec &= ec - 1;
-        if (cnt < kMaxInsert) {
-            pos[cnt++] = b;
-            e.set |= 1ull << b;
-        } else {
-            e.check |= 1ull << b;
-        }
+// ------------------------------------------------------ tiled reverse sweep
+// Both vectors of a tile sit in LDS; each register sweep loads the same group
+// of psi and lam and undoes the sweep's gates on both.  A parametrised gate
+// is preceded by a probe record that adds the group's share of
+// Im <lam| M |psi> to the gate's slot (wave reduction, then one LDS atomic
+// per wave).  The slot sums of a
+// workgroup cover all its tiles and are written once at the end.
+int adjoint_tile_qubits(int dtype) { return dtype == SV_C64 ? 12 : 11; } // 2 x 32 KiB of LDS
+
+template <typename T, int W, int P>
+__device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
+                                            const uint32_t (&li)[1 << W], const TileGate &G, uint32_t cin) {
+    constexpr int D = 1 << W;
+    const cpx<T> m0 = gmat<T>(G, 0), m1 = gmat<T>(G, 1), m2 = gmat<T>(G, 2), m3 = gmat<T>(G, 3);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (j & (1 << P)) continue;
+        if ((li[j] & cin) != cin) continue;
+        const int c = j | (1 << P);
+        const cpx<T> z0 = cfma(m0, v[j], cmul(m1, v[c]));
+        const cpx<T> z1 = cfma(m2, v[j], cmul(m3, v[c]));
+        acc += im_conj_mul(w[j], z0) + im_conj_mul(w[c], z1);
     }
-    std::sort(pos, pos + cnt);
-    e.n_pos = cnt;
-    for (int i = 0; i < cnt; ++i) e.pos[i] = pos[i];
-    *np = cnt;
-    return e;
+    return acc;
 }
 
-hipError_t launch_adjoint_param(void *psi, void *lam, int n, int dtype, int t, uint64_t ctrl,
-                                const double *udag, const double *probe, double *partials,
-                                hipStream_t s) {
+template <typename T, int W>
+__device__ __forceinline__ double probe_gate(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
+                                             const uint32_t (&li)[1 << W], const TileGate &G) {
+    const int p = G.b0;
+    const uint32_t cin = G.cin;
+    if (p == 0) return probe_pos<T, W, 0>(v, w, li, G, cin);
+    if constexpr (W >= 2) if (p == 1) return probe_pos<T, W, 1>(v, w, li, G, cin);
+    if constexpr (W >= 3) if (p == 2) return probe_pos<T, W, 2>(v, w, li, G, cin);
+    if constexpr (W >= 4) if (p == 3) return probe_pos<T, W, 3>(v, w, li, G, cin);
+    return 0.0;
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_adjoint_tile(typename AV<T>::type *psi, typename AV<T>::type *lam,
+                                                      TileSpec sp, int m, const TileSweep *__restrict__ sweeps,
+                                                      int n_sweeps, const TileGate *__restrict__ gates,
+                                                      int slot0, int n_slots, double *partials,
+                                                      uint64_t n_tiles) {
+    using V = AV<T>;
+    constexpr int D = 1 << W;
+    extern __shared__ char lds_raw[];
+    const uint32_t tsize = 1u << m, tvec = tsize >> V::bits;
+    cpx<T> *lp = reinterpret_cast<cpx<T> *>(lds_raw);
+    cpx<T> *ll = lp + tsize;
+    __shared__ double slot_acc[kMaxAdjSlots];
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) slot_acc[i] = 0.0;
+    const uint32_t n_groups = tsize >> W;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint64_t base = tile << sp.L;
+        for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
+        for (uint32_t l = threadIdx.x; l < tvec; l += blockDim.x) {
+            const uint32_t la = l << V::bits;
+            uint64_t g = base | (la & ((1u << sp.L) - 1u));
+            const uint32_t hi = la >> sp.L;
+            for (int i = 0; i < sp.K; ++i)
+                if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
+            const typename V::type a = psi[g >> V::bits], b = lam[g >> V::bits];
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) {
+                lp[lds_phys<T>(la + k)] = V::get(a, k);
+                ll[lds_phys<T>(la + k)] = V::get(b, k);
+            }
+        }
+        __syncthreads();
+        int goff = 0;
+        for (int si = 0; si < n_sweeps; ++si) {
+            const TileSweep &S = sweeps[si];
+            const int ng = S.n_gates;
+            uint32_t F[D], PF[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                uint32_t f = 0;
+#pragma unroll
+                for (int b = 0; b < W; ++b)
+                    if ((j >> b) & 1) f |= 1u << S.qpos[b];
+                F[j] = f;
+                PF[j] = lds_phys<T>(f);
+            }
+            // every lane runs the same number of iterations (the probe's wave
+            // reduction needs all 64 lanes); lanes past the last group add 0
+            for (uint32_t g0 = 0; g0 < n_groups; g0 += blockDim.x) {
+                const uint32_t g = g0 + threadIdx.x;
+                const bool act = g < n_groups;
+                uint32_t gb = act ? g : 0u;
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    const uint32_t low = (1u << S.qpos[b]) - 1u;
+                    gb = (gb & low) | ((gb & ~low) << 1);
+                }
+                const uint32_t pg = lds_phys<T>(gb);
+                cpx<T> v[D], w[D];
+                uint32_t li[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    li[j] = gb | F[j];
+                    v[j] = lp[pg ^ PF[j]];
+                    w[j] = ll[pg ^ PF[j]];
+                }
+                for (int gi = 0; gi < ng; ++gi) {
+                    const TileGate &G = gates[goff + gi];
+                    if ((base & G.cout) != G.cout) continue; // uniform
+                    if (G.kind == SK_PARAM) {
+                        const double mine = act ? probe_gate<T, W>(v, w, li, G) : 0.0;
+                        const double c = wave_sum_d(mine);
+                        if ((threadIdx.x & 63) == 0) atomicAdd(&slot_acc[G.b1], c);
+
+                    } else if (G.cin == 0) {
+                        sweep_gate_t<T, W, false>(v, li, G);
+                        sweep_gate_t<T, W, false>(w, li, G);
+                    } else {
+                        sweep_gate_t<T, W, true>(v, li, G);
+                        sweep_gate_t<T, W, true>(w, li, G);
+                    }
+                }
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        lp[pg ^ PF[j]] = v[j];
+                        ll[pg ^ PF[j]] = w[j];
+                    }
+                }
+            }
+            goff += ng;
+            __syncthreads();
+        }
+        for (uint32_t l = threadIdx.x; l < tvec; l += blockDim.x) {
+            const uint32_t la = l << V::bits;
+            uint64_t g = base | (la & ((1u << sp.L) - 1u));
+            const uint32_t hi = la >> sp.L;
+            for (int i = 0; i < sp.K; ++i)
+                if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
+            typename V::type a, b;
+#pragma unroll
+            for (int k = 0; k < V::amps; ++k) {
+                V::put(a, k, lp[lds_phys<T>(la + k)]);
+                V::put(b, k, ll[lds_phys<T>(la + k)]);
+            }
+            psi[g >> V::bits] = a;
+            lam[g >> V::bits] = b;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x)
+        partials[(size_t)(slot0 + i) * gridDim.x + blockIdx.x] = slot_acc[i];
+}
+
+hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,
+                               const TileSweep *dev_sweeps, int n_sweeps, const TileGate *dev_gates,
+                               int slot0, int n_slots, double *partials, int n_blocks, hipStream_t s) {
+    const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
-    const uint64_t n_el = (1ull << n) >> vbits;
-    uint32_t lane_ctrl = 0;
-    int np = 0;
-    const unsigned grid = (unsigned)adjoint_blocks();
-    if (t < vbits) {
-        Enum e = adj_enum(vbits, 0, false, ctrl, &lane_ctrl, &np);
-        Mat2<float> u, p;
-        for (int i = 0; i < 4; ++i) {
-            u.m[i] = {(float)udag[2 * i], (float)udag[2 * i + 1]};
-            p.m[i] = {(float)probe[2 * i], (float)probe[2 * i + 1]};
-        }
-        k_adjoint_param_q0<<<grid, kAdjThreads, 0, s>>>((float4 *)psi, (float4 *)lam, e, n_el >> np, u, p,
-                                                        partials);
-        return hipGetLastError();
+    if (m > n || m > adjoint_tile_qubits(dtype) || spec.L < vbits || n_slots > kMaxAdjSlots || m < 1)
+        return hipErrorInvalidValue;
+    const uint64_t n_tiles = 1ull << (n - m);
+    if ((uint64_t)n_blocks > n_tiles) return hipErrorInvalidValue; // every workgroup owns a tile
+    const size_t lds = 2 * (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
+    const int W = std::min(m, sweep_width(dtype));
+#define SV_ADJ_CASE(TT, VT, WW)                                                                    \
+    if (W == WW) {                                                                                 \
+        (void)hipFuncSetAttribute((const void *)k_adjoint_tile<TT, WW>,                            \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+        k_adjoint_tile<TT, WW><<<n_blocks, 256, lds, s>>>((VT *)psi, (VT *)lam, spec, m, dev_sweeps,\
+                                                          n_sweeps, dev_gates, slot0, n_slots,     \
+                                                          partials, n_tiles);                      \
+        return hipGetLastError();                                                                  \
     }
-    const int te = t - vbits;
-    Enum e = adj_enum(vbits, te, true, ctrl, &lane_ctrl, &np);
-    const uint64_t count = n_el >> np;
     if (dtype == SV_C64) {
-        Mat2<float> u, p;
-        for (int i = 0; i < 4; ++i) {
-            u.m[i] = {(float)udag[2 * i], (float)udag[2 * i + 1]};
-            p.m[i] = {(float)probe[2 * i], (float)probe[2 * i + 1]};
-        }
-        k_adjoint_param<float><<<grid, kAdjThreads, 0, s>>>((float4 *)psi, (float4 *)lam, e, te, count, u, p,
-                                                            lane_ctrl, partials);
+        SV_ADJ_CASE(float, float4, 4)
+        SV_ADJ_CASE(float, float4, 3)
+        SV_ADJ_CASE(float, float4, 2)
+        SV_ADJ_CASE(float, float4, 1)
     } else {
-        Mat2<double> u, p;
-        for (int i = 0; i < 4; ++i) {
-            u.m[i] = {udag[2 * i], udag[2 * i + 1]};
-            p.m[i] = {probe[2 * i], probe[2 * i + 1]};
-        }
-        k_adjoint_param<double><<<grid, kAdjThreads, 0, s>>>((double2 *)psi, (double2 *)lam, e, te, count, u,
-                                                             p, lane_ctrl, partials);
+        SV_ADJ_CASE(double, double2, 3)
+        SV_ADJ_CASE(double, double2, 2)
+        SV_ADJ_CASE(double, double2, 1)
     }
-    return hipGetLastError();
+#undef SV_ADJ_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sum_slots(const double *partials, int n_slots, int n_blocks, double *out,

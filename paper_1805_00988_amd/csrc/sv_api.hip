@@ -372,30 +372,64 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
 // Group the pass's gates (in order) into sweeps of at most W register
 // qubits; diagonal one-qubit gates join the current sweep whatever their
 // target, since they act per amplitude.
-static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w,
+// Probe of a parametrised gate in an adjoint pass: slot within the pass and
+// the 2x2 probe matrix (complex, interleaved).
+struct Probe {
+    int slot;
+    double M[8];
+};
+
+static TileGate encode_probe(const TileSpec &sp, const std::vector<int> &qset, const Gate &g, const Probe &pr,
                              bool f32) {
+    TileGate r;
+    std::memset(&r, 0, sizeof(r));
+    encode_controls(sp, g.ctrl, &r);
+    r.kind = SK_PARAM;
+    const int lb = local_bit(sp, g.t[0]);
+    r.b0 = (int)(std::find(qset.begin(), qset.end(), lb) - qset.begin());
+    r.b1 = pr.slot;
+    put_matrix(r, pr.M, 4, f32);
+    return r;
+}
+
+// Group the pass's gates (in order) into sweeps of at most W register
+// qubits; diagonal one-qubit gates join the current sweep whatever their
+// target, since they act per amplitude.  With probes (adjoint passes), a
+// parametrised gate needs its target in registers and is encoded as a probe
+// record followed by its own record.
+static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w, bool f32,
+                             const std::vector<const Probe *> *probes = nullptr) {
     PassCode pc;
     pc.sp = sp;
     pc.m = sp.L + sp.K;
     const int W = std::min(pc.m, sweep_w);
     std::vector<int> qset;
-    std::vector<const Gate *> cur;
+    std::vector<size_t> cur;
+    auto probe_of = [&](size_t i) -> const Probe * { return probes ? (*probes)[i] : nullptr; };
     auto close = [&]() {
         if (cur.empty()) return;
         for (int b = 0; (int)qset.size() < W && b < pc.m; ++b)
             if (std::find(qset.begin(), qset.end(), b) == qset.end()) qset.push_back(b);
         std::sort(qset.begin(), qset.end());
         TileSweep sw{};
-        sw.n_gates = (int)cur.size();
+        sw.n_gates = 0;
+        for (size_t i : cur) {
+            if (const Probe *pr = probe_of(i)) {
+                pc.gates.push_back(encode_probe(sp, qset, *gs[i], *pr, f32));
+                ++sw.n_gates;
+            }
+            pc.gates.push_back(encode_sweep_gate(sp, qset, *gs[i], f32));
+            ++sw.n_gates;
+        }
         for (int j = 0; j < kSweepW; ++j) sw.qpos[j] = j < W ? qset[j] : 0;
         pc.sweeps.push_back(sw);
-        for (const Gate *g : cur) pc.gates.push_back(encode_sweep_gate(sp, qset, *g, f32));
         cur.clear();
         qset.clear();
     };
-    for (const Gate *g : gs) {
-        if (is_diag1(*g)) {
-            cur.push_back(g);
+    for (size_t i = 0; i < gs.size(); ++i) {
+        const Gate *g = gs[i];
+        if (is_diag1(*g) && !probe_of(i)) {
+            cur.push_back(i);
             continue;
         }
         std::vector<int> need;
@@ -408,7 +442,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
             const int lb = local_bit(sp, g->t[j]);
             if (std::find(qset.begin(), qset.end(), lb) == qset.end()) qset.push_back(lb);
         }
-        cur.push_back(g);
+        cur.push_back(i);
     }
     close();
     return pc;
@@ -1385,16 +1419,85 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, con
             return fail(SV_EINVAL, "op " + std::to_string(i) + ": only RX RY RZ U1 can carry a parameter");
         ++n_param_gates;
     }
-    const int B = adjoint_blocks();
-    const size_t slots = (size_t)n_param_gates + 1;
-    if ((rc = ensure_scratch(h, slots * B + slots))) return rc;
-    double *partials = h->d_scratch, *sums = h->d_scratch + slots * B;
+    // reverse list: undo of every gate (last first), parametrised ones with a probe
+    std::vector<Gate> rev;
+    std::vector<Probe> probes_store;
+    std::vector<int> rev_param;   // param_index of each reversed gate, -1 if fixed
+    std::vector<double> rev_factor;
+    rev.reserve(gs.size());
+    probes_store.reserve(gs.size());
+    for (int g = n_ops - 1; g >= 0; --g) {
+        rev.push_back(dagger(gs[g]));
+        rev_param.push_back(ops[g].param_index);
+        double M[8] = {0, 0, 0, 0, 0, 0, 0, 0}, f = 0.0;
+        if (ops[g].param_index >= 0) probe_of(ops[g].kind, M, &f);
+        rev_factor.push_back(f);
+        Probe pr{};
+        std::memcpy(pr.M, M, sizeof(M));
+        probes_store.push_back(pr);
+    }
+    const int mmax = std::min(h->n, adjoint_tile_qubits(h->dtype));
+    const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
+    const int B = (int)std::min<uint64_t>((uint64_t)adjoint_blocks(), 1ull << (h->n - mmax));
+    std::vector<Pass> passes = schedule(rev, h->n, mmax, lmin);
+    // split passes holding more parametrised gates than one launch accumulates
+    std::vector<Pass> split;
+    for (const Pass &p : passes) {
+        Pass cur;
+        int np = 0;
+        for (int gi : p.gates) {
+            if (rev_param[gi] >= 0 && np == kMaxAdjSlots) {
+                split.push_back(cur);
+                cur = Pass{};
+                np = 0;
+            }
+            cur.gates.push_back(gi);
+            if (rev_param[gi] >= 0) ++np;
+        }
+        if (!cur.gates.empty()) split.push_back(cur);
+    }
+    // compile: slots numbered globally in sweep order
+    std::vector<PassCode> code(split.size());
+    std::vector<int> slot0(split.size()), nslot(split.size());
+    std::vector<int> slot_param, slot_rev;
+    std::vector<size_t> offs(split.size());
+    size_t total = 0;
+    for (size_t pi = 0; pi < split.size(); ++pi) {
+        uint64_t needed = 0;
+        std::vector<const Gate *> ptrs;
+        std::vector<const Probe *> prs;
+        slot0[pi] = (int)slot_param.size();
+        int ns = 0;
+        for (int gi : split[pi].gates) {
+            needed |= rev[gi].tmask();
+            ptrs.push_back(&rev[gi]);
+            if (rev_param[gi] >= 0) {
+                probes_store[gi].slot = ns++;
+                prs.push_back(&probes_store[gi]);
+                slot_param.push_back(rev_param[gi]);
+                slot_rev.push_back(gi);
+            } else {
+                prs.push_back(nullptr);
+            }
+        }
+        nslot[pi] = ns;
+        TileSpec sp{};
+        tile_layout(h->n, mmax, lmin, needed, &sp);
+        code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64, &prs);
+        offs[pi] = total;
+        total += align256(code[pi].bytes());
+    }
+    const size_t n_slots = slot_param.size();
+    const size_t loss_n = (size_t)adjoint_blocks();
+    if ((rc = ensure_scratch(h, loss_n + n_slots * B + 1 + n_slots))) return rc;
+    double *partials = h->d_scratch;                       // loss partials, then slot partials
+    double *sums = h->d_scratch + loss_n + n_slots * B;    // loss, then one sum per slot
     hipStream_t saved = lam->stream;
     SV_HIP(hipStreamSynchronize(saved));
     lam->stream = h->stream; // every launch of the sweep is ordered on h's stream
-    auto restore = [&](int code) {
+    auto restore = [&](int code_) {
         lam->stream = saved;
-        return code;
+        return code_;
     };
     {
         Timed tm(h, K_ADJOINT, 2.0 * state_bytes(h));
@@ -1402,47 +1505,34 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, con
                                            partials, h->stream);
         if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_init"));
     }
-    std::vector<int> slot_param(slots, -1);
-    std::vector<double> slot_factor(slots, 0.0);
-    std::vector<Gate> pending;
-    auto flush = [&]() -> int {
-        if (pending.empty()) return SV_OK;
-        int r = run_gates(h, pending, SV_RUN_TILED);
-        if (!r) r = run_gates(lam, pending, SV_RUN_TILED);
-        pending.clear();
-        return r;
-    };
-    int slot = 1;
-    for (int g = n_ops - 1; g >= 0; --g) {
-        if (ops[g].param_index < 0) {
-            pending.push_back(dagger(gs[g]));
-            continue;
-        }
-        if ((rc = flush())) return restore(rc);
-        double M[8], f;
-        probe_of(ops[g].kind, M, &f);
-        const Gate d = dagger(gs[g]);
-        Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(d.ctrl)));
-        hipError_t e = launch_adjoint_param(h->amps, lam->amps, h->n, h->dtype, d.t[0], d.ctrl, d.U, M,
-                                            partials + (size_t)slot * B, h->stream);
-        if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_param"));
-        slot_param[slot] = ops[g].param_index;
-        slot_factor[slot] = f;
-        ++slot;
+    if (total) {
+        if ((rc = ensure_arena(h, total))) return restore(rc);
+        if ((rc = stage_wait(h))) return restore(rc);
+        for (size_t pi = 0; pi < split.size(); ++pi) stage_pass(h, code[pi], offs[pi]);
+        if ((rc = upload_arena(h, total))) return restore(rc);
     }
-    if ((rc = flush())) return restore(rc);
-    hipError_t e = launch_sum_slots(partials, (int)slots, B, sums, h->stream);
+    for (size_t pi = 0; pi < split.size(); ++pi) {
+        const PassCode &pc = code[pi];
+        const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + offs[pi]);
+        const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + offs[pi] +
+                                                                align256(pc.sweeps.size() * sizeof(TileSweep)));
+        Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h));
+        hipError_t e = launch_adjoint_tile(h->amps, lam->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt,
+                                           slot0[pi], nslot[pi], partials + loss_n, B, h->stream);
+        if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_tile"));
+    }
+    hipError_t e = launch_sum_slots(partials, 1, (int)loss_n, sums, h->stream);
+    if (e == hipSuccess) e = launch_sum_slots(partials + loss_n, (int)n_slots, B, sums + 1, h->stream);
     if (e != hipSuccess) return restore(hip_fail(e, "launch_sum_slots"));
-    std::vector<double> out(slots);
-    e = hipMemcpyAsync(out.data(), sums, slots * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    std::vector<double> out(n_slots + 1);
+    e = hipMemcpyAsync(out.data(), sums, out.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return restore(hip_fail(e, "adjoint result copy"));
     *host_loss = out[0];
     for (int p = 0; p < n_params; ++p) host_grad[p] = 0.0;
-    for (size_t sl = 1; sl < slots; ++sl) host_grad[slot_param[sl]] += slot_factor[sl] * out[sl];
+    for (size_t sl = 0; sl < n_slots; ++sl) host_grad[slot_param[sl]] += rev_factor[slot_rev[sl]] * out[sl + 1];
     return restore(SV_OK);
 }
-
 
 int sv_batch_create(int n_circuits, const int *widths, const int64_t *op_offsets, const sv_op *ops,
                     const double *params, int n_params, int dtype, uint64_t z_mask, int flags,

@@ -79,6 +79,8 @@ enum SweepKind : int32_t {
     SK_DIAG = 3, // diag(d0, d1) on tile bit b0 (any position); m: d0, d1
     SK_SWAP = 4, // X: exchange the pair
     SK_2Q = 5,   // 4x4 on sweep positions b0 < b1 (bit 0 of the matrix index <-> b0)
+    SK_PARAM = 6 // adjoint sweep: add Im<lam|M|psi> for M (entries 0-3) on position b0
+                 // to slot b1; the undo of the gate follows as its own record
 };
 struct TileGate {
     int32_t kind;
@@ -183,10 +185,15 @@ int adjoint_blocks();
 hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int n_terms,
                                const uint64_t *masks, const double *coeffs, double *partials,
                                hipStream_t s);
-hipError_t launch_adjoint_param(void *psi, void *lam, int n, int dtype, int t, uint64_t ctrl,
-                                const double *udag, const double *probe, double *partials,
-                                hipStream_t s);
 hipError_t launch_sum_slots(const double *partials, int n_slots, int n_blocks, double *out,
                             hipStream_t s);
+// One tile pass of the adjoint sweep over psi and lam (both staged in LDS).
+// Probes of the pass's parametrised gates accumulate per workgroup and are
+// written to partials[(slot0 + i) * n_blocks + workgroup] for i < n_slots.
+hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,
+                               const TileSweep *dev_sweeps, int n_sweeps, const TileGate *dev_gates,
+                               int slot0, int n_slots, double *partials, int n_blocks, hipStream_t s);
+int adjoint_tile_qubits(int dtype);
+constexpr int kMaxAdjSlots = 128;
 
 } // namespace sv
