@@ -59,9 +59,13 @@ enum sv_status {
     SV_EUNSUPPORTED = -4  /* valid request the library does not implement */
 };
 
-/* Arithmetic of sv_apply_fused blocks. */
+/* Arithmetic of sv_apply_fused blocks.  Blocks run on the matrix cores
+ * (MFMA) whenever the state is large enough to fill whole MFMA tiles (2^10
+ * amplitudes for 5-qubit blocks), narrower blocks padded to 4 qubits; tiny
+ * states use the vector ALUs in the same precision. */
 enum sv_prec {
-    SV_PREC_NATIVE = 0,     /* the state's own precision on the vector ALUs */
+    SV_PREC_NATIVE = 0,     /* the state's own precision: FP32 products and sums
+                               for complex64, FP64 for complex128 */
     SV_PREC_FP32 = 1,       /* FP32 matrix-core (MFMA) products, FP32 accumulate */
     SV_PREC_SPLIT_BF16 = 2  /* each FP32 operand split into bf16 hi + lo; three
                                bf16 MFMA products (hi*hi, hi*lo, lo*hi) with FP32
@@ -135,8 +139,7 @@ int sv_apply_gate(sv_handle h, int k, const int *targets, uint64_t ctrl_mask, co
  * several gates computed by sv_fuse: every group of 2^k amplitudes differing
  * only in the bits qubits[0..k-1] is multiplied by U (bit j <-> qubits[j]).
  * prec selects the arithmetic (enum sv_prec); SV_PREC_FP32 and
- * SV_PREC_SPLIT_BF16 need k >= 4 and run on the matrix cores, and require an
- * SV_C64 state.  SV_EUNSUPPORTED for other combinations. */
+ * SV_PREC_SPLIT_BF16 require an SV_C64 state (SV_EUNSUPPORTED otherwise). */
 int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int prec);
 
 /* Sec. 2.4: write p_x = re^2 + im^2 for every x to dev_out (float[2^n] for

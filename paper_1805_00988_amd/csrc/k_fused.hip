@@ -17,6 +17,7 @@
 // accumulates hi*hi + hi*lo + lo*hi in FP32 with v_mfma_f32_{32x32x16,
 // 16x16x32}_bf16.
 #include "sv_internal.hpp"
+#include "tile_sweep.hpp"
 
 #include <algorithm>
 
@@ -25,6 +26,7 @@ namespace sv {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFuseThreads = 512;
 
@@ -35,7 +37,9 @@ __device__ __forceinline__ uint32_t deposit(uint32_t x, const int *pos, int nbit
     return r;
 }
 
-// Tile staging shared with the gate tile pass (same index mapping).
+// Tile staging shared with the gate tile pass (same index mapping and the
+// same swizzled LDS layout; lds_phys is linear over XOR, so the address of a
+// deposit of disjoint index parts is the XOR of the parts' addresses).
 __device__ __forceinline__ uint64_t tile_base(const TileSpec &sp, uint64_t tile) {
     uint64_t base = tile << sp.L;
     for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
@@ -71,10 +75,10 @@ __device__ __forceinline__ void stage_in(const typename V16<T>::type *v, cpx<T> 
         const uint32_t la = l << vb;
         const typename V16<T>::type w = v[tile_addr(sp, base, la) >> vb];
         if constexpr (vb == 1) {
-            lds[la] = cpx<T>{w.x, w.y};
-            lds[la + 1] = cpx<T>{w.z, w.w};
+            lds[lds_phys<T>(la)] = cpx<T>{w.x, w.y};
+            lds[lds_phys<T>(la + 1)] = cpx<T>{w.z, w.w};
         } else {
-            lds[la] = cpx<T>{w.x, w.y};
+            lds[lds_phys<T>(la)] = cpx<T>{w.x, w.y};
         }
     }
 }
@@ -87,9 +91,11 @@ __device__ __forceinline__ void stage_out(typename V16<T>::type *v, const cpx<T>
         const uint32_t la = l << vb;
         typename V16<T>::type w;
         if constexpr (vb == 1) {
-            w = float4{lds[la].re, lds[la].im, lds[la + 1].re, lds[la + 1].im};
+            const cpx<T> a = lds[lds_phys<T>(la)], b = lds[lds_phys<T>(la + 1)];
+            w = float4{a.re, a.im, b.re, b.im};
         } else {
-            w = double2{lds[la].re, lds[la].im};
+            const cpx<T> a = lds[lds_phys<T>(la)];
+            w = double2{a.re, a.im};
         }
         v[tile_addr(sp, base, la) >> vb] = w;
     }
@@ -117,20 +123,20 @@ __global__ __launch_bounds__(256) void k_dense_native(typename V16<T>::type *v, 
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
             const cpx<T> *U = reinterpret_cast<const cpx<T> *>(base_ptr + B.op_off);
-            uint32_t F[D];
+            uint32_t PF[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) F[j] = deposit((uint32_t)j, B.bp.qpos, K);
+            for (int j = 0; j < D; ++j) PF[j] = lds_phys<T>(deposit((uint32_t)j, B.bp.qpos, K));
             for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
-                const uint32_t gb = deposit(g, B.bp.gpos, B.bp.ng);
+                const uint32_t pg = lds_phys<T>(deposit(g, B.bp.gpos, B.bp.ng));
                 cpx<T> x[D];
 #pragma unroll
-                for (int j = 0; j < D; ++j) x[j] = lds[gb | F[j]];
+                for (int j = 0; j < D; ++j) x[j] = lds[pg ^ PF[j]];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
                     cpx<T> acc = cmul(U[i * D], x[0]);
 #pragma unroll
                     for (int j = 1; j < D; ++j) acc = cfma(U[i * D + j], x[j], acc);
-                    lds[gb | F[i]] = acc;
+                    lds[pg ^ PF[i]] = acc;
                 }
             }
             __syncthreads();
@@ -219,20 +225,25 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
 #pragma unroll
                     for (int hl = 0; hl < 2; ++hl) bbf[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
         }
-        const uint32_t Fcol = deposit((uint32_t)r, bp.qpos, K); // this lane's output amplitude
-        const uint32_t Grow = deposit((uint32_t)r, bp.gpos, bp.ng);
+        // Addresses: A element j of group row, and output (row, col), are
+        // XORs of swizzled deposits of disjoint index parts (see above).
+        auto PQ = [&](uint32_t j) { return lds_phys<float>(deposit(j, bp.qpos, K)); };
+        auto PG = [&](uint32_t g) { return lds_phys<float>(deposit(g, bp.gpos, bp.ng)); };
+        const uint32_t pcol = PQ((uint32_t)r);           // this lane's output amplitude
+        const uint32_t prow_lane = PG((uint32_t)r);      // this lane's A row
+        const uint32_t pout_lane = PG(ROWS == 32 ? 4u * kk : 4u * kk) ^ pcol;
+        // per-lane part of the A amplitude index
+        const uint32_t pa_lane = PREC == 1 ? PQ((uint32_t)kk) : PQ(ROWS == 32 ? 8u * kk : 8u * (kk & 1));
         for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-            const uint32_t gw = deposit(wt * ROWS, bp.gpos, bp.ng);
-            const uint32_t arow = gw | Grow;
+            const uint32_t pgw = PG(wt * ROWS);
+            const uint32_t arow = pgw ^ prow_lane ^ pa_lane;
             accT yr = {}, yi = {};
             if constexpr (PREC == 1) {
-                // K index q = KS/2 ... : first half Re, second half Im of amp j
                 constexpr int half = KS / 2;
                 constexpr int per = ROWS == 32 ? 2 : 4; // K per MFMA
 #pragma unroll
                 for (int s = 0; s < half; ++s) {
-                    const int j = per * s + kk;
-                    const cpx<float> x = lds[arow | deposit((uint32_t)j, bp.qpos, K)];
+                    const cpx<float> x = lds[arow ^ PQ((uint32_t)(per * s))];
                     if constexpr (ROWS == 32) {
                         yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bf32[0][s], yr, 0, 0, 0);
                         yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bf32[1][s], yi, 0, 0, 0);
@@ -253,13 +264,12 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
                         bf16x8 rh, rl, ih, il;
 #pragma unroll
                         for (int e = 0; e < 8; ++e) {
-                            const int j = 16 * s2 + 8 * kk + e;
-                            const cpx<float> x = lds[arow | deposit((uint32_t)j, bp.qpos, K)];
-                            const __bf16 a = bf16_hi(x.re), b = bf16_hi(x.im);
+                            const cpx<float> x = lds[arow ^ PQ((uint32_t)(16 * s2 + e))];
+                            const __bf16 a = bf16_hi(x.re), c = bf16_hi(x.im);
                             rh[e] = a;
                             rl[e] = bf16_lo(x.re, a);
-                            ih[e] = b;
-                            il[e] = bf16_lo(x.im, b);
+                            ih[e] = c;
+                            il[e] = bf16_lo(x.im, c);
                         }
 #pragma unroll
                         for (int p = 0; p < 2; ++p) {
@@ -277,8 +287,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
                     bf16x8 ah, al;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const int j = 8 * (kk & 1) + e;
-                        const cpx<float> x = lds[arow | deposit((uint32_t)j, bp.qpos, K)];
+                        const cpx<float> x = lds[arow ^ PQ((uint32_t)e)];
                         const float c = kk < 2 ? x.re : x.im;
                         const __bf16 a = bf16_hi(c);
                         ah[e] = a;
@@ -294,11 +303,11 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
                 }
             }
             // D[row][col]: col = r (output amplitude), rows from the accumulator layout
+            const uint32_t pout = pgw ^ pout_lane;
 #pragma unroll
             for (int q = 0; q < ACC; ++q) {
-                const int row = ROWS == 32 ? 8 * (q / 4) + 4 * kk + (q % 4) : 4 * kk + q;
-                const uint32_t g = gw | deposit((uint32_t)row, bp.gpos, bp.ng);
-                lds[g | Fcol] = cpx<float>{yr[q], yi[q]};
+                const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
+                lds[pout ^ PG(rq)] = cpx<float>{yr[q], yi[q]};
             }
         }
         __syncthreads();
@@ -307,6 +316,89 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec
         __syncthreads();
     }
     (void)D;
+}
+
+
+// ---------------------------------------------------- MFMA, complex128
+// FP64 matrix cores (v_mfma_f64_16x16x4f64, operands laid out as the FP32
+// 16x16x4 one; result element q of lane l is row 4q + l/16, column l%16, as
+// measured on the device): wave-tiles of 16 groups; K
+// index 4s + kk of [Re x | Im x] (lane kk = lane / 16 loads amplitude
+// 4s + kk and uses its real part at K-step s, its imaginary part at K-step
+// s + D/4); D/16 output tiles of 16 amplitudes per part.  Operand fragments:
+// frag[((part * NT + nt) * KS + s) * 64 + lane] (double), kept in registers
+// for k = 4 and read from L1 per K-step for k = 5.
+template <int K>
+__global__ __launch_bounds__(kFuseThreads) void k_dense_mfma64(double2 *v, TileSpec sp, int m,
+                                                               const DenseBlock *__restrict__ blocks,
+                                                               int n_blocks, const char *__restrict__ base_ptr,
+                                                               uint64_t n_tiles) {
+    constexpr int D = 1 << K;
+    constexpr int NT = D / 16;     // output tiles per part
+    constexpr int KS = 2 * D / 4;  // K-steps over 2D
+    constexpr int HALF = KS / 2;
+    constexpr bool PRELOAD = K == 4;
+    extern __shared__ char lds_raw[];
+    cpx<double> *lds = reinterpret_cast<cpx<double> *>(lds_raw);
+    const uint32_t tsize = 1u << m;
+    const uint32_t n_wt = (tsize >> K) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int r = lane & 15, kk = lane >> 4;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t base = tile_base(sp, tile);
+        stage_in<double>(v, lds, sp, base, tsize);
+        __syncthreads();
+        for (int b = 0; b < n_blocks; ++b) {
+            const DenseBlock &B = blocks[b];
+            const BlockPos &bp = B.bp;
+            const double *frag = reinterpret_cast<const double *>(base_ptr + B.op_off);
+            double bpre[PRELOAD ? 2 * NT * KS : 1];
+            if constexpr (PRELOAD) {
+#pragma unroll
+                for (int i = 0; i < 2 * NT * KS; ++i) bpre[i] = frag[i * 64 + lane];
+            }
+            auto PQ = [&](uint32_t j) { return lds_phys<double>(deposit(j, bp.qpos, K)); };
+            auto PG = [&](uint32_t g) { return lds_phys<double>(deposit(g, bp.gpos, bp.ng)); };
+            const uint32_t lane_a = PG((uint32_t)r) ^ PQ((uint32_t)kk);
+            // FP64 16x16x4 result layout: element q of lane (r, kk) is row 4q + kk
+            const uint32_t lane_out = PG((uint32_t)kk) ^ PQ((uint32_t)r);
+            for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
+                const uint32_t pgw = PG(wt * 16u);
+                const uint32_t arow = pgw ^ lane_a;
+                doublex4 acc[2][NT];
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[p][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < HALF; ++s) {
+                    const cpx<double> x = lds[arow ^ PQ((uint32_t)(4 * s))];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const int i0 = (p * NT + nt) * KS + s, i1 = i0 + HALF;
+                            const double b0 = PRELOAD ? bpre[PRELOAD ? i0 : 0] : frag[i0 * 64 + lane];
+                            const double b1 = PRELOAD ? bpre[PRELOAD ? i1 : 0] : frag[i1 * 64 + lane];
+                            acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, b0, acc[p][nt], 0, 0, 0);
+                            acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, b1, acc[p][nt], 0, 0, 0);
+                        }
+                }
+                // D: lane holds rows 4q + kk of output tile nt, column r
+                const uint32_t pout = pgw ^ lane_out;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        lds[pout ^ PG(4u * q) ^ PQ((uint32_t)(16 * nt))] =
+                            cpx<double>{acc[0][nt][q], acc[1][nt][q]};
+            }
+            __syncthreads();
+        }
+        stage_out<double>(v, lds, sp, base, tsize);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- launch
@@ -320,6 +412,21 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1024);
+    if (prec == kPrecMfma64) {
+        if (dtype != SV_C128 || k < 4 || ((1u << m) >> k) % 16) return hipErrorInvalidValue;
+        if (k == 4) {
+            (void)hipFuncSetAttribute((const void *)k_dense_mfma64<4>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            k_dense_mfma64<4><<<grid, kFuseThreads, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks,
+                                                              dev_base, n_tiles);
+        } else {
+            (void)hipFuncSetAttribute((const void *)k_dense_mfma64<5>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            k_dense_mfma64<5><<<grid, kFuseThreads, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks,
+                                                              dev_base, n_tiles);
+        }
+        return hipGetLastError();
+    }
     if (prec != SV_PREC_NATIVE) {
         if (dtype != SV_C64 || k < 4) return hipErrorInvalidValue;
         const int rows = k == 5 ? 32 : 16;

@@ -736,6 +736,34 @@ static void make_fragments(const std::complex<double> *U, int k, int prec, char 
     }
 }
 
+// FP64 MFMA operand (complex128 blocks): frag[((p * NT + nt) * KS + s) * 64 + lane]
+// = B_p[4s + lane/16][16nt + lane%16], NT = D/16, KS = D/2.
+static size_t frag64_bytes(int k) {
+    const int D = 1 << k;
+    return (size_t)2 * (D / 16) * (D / 2) * 64 * sizeof(double);
+}
+
+static void make_fragments64(const std::complex<double> *U, int k, char *out) {
+    const int D = 1 << k, NT = D / 16, KS = D / 2;
+    double *f = reinterpret_cast<double *>(out);
+    for (int p = 0; p < 2; ++p)
+        for (int nt = 0; nt < NT; ++nt)
+            for (int st = 0; st < KS; ++st)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int krow = 4 * st + lane / 16, col = 16 * nt + lane % 16;
+                    const bool top = krow < D;
+                    const std::complex<double> u = U[(size_t)col * D + (top ? krow : krow - D)];
+                    const double val = p == 0 ? (top ? u.real() : -u.imag()) : (top ? u.imag() : u.real());
+                    f[((p * NT + nt) * KS + st) * 64 + lane] = val;
+                }
+}
+
+static bool mfma64_ok(const sv_state *h, int k) {
+    if (h->dtype != SV_C128 || (k != 4 && k != 5)) return false;
+    const int m = std::min(h->n, fused_tile_qubits(h->dtype));
+    return m >= k && ((1u << m) >> k) % 16 == 0;
+}
+
 // Whether a k-qubit MFMA block can run on this state (whole wave-tiles).
 static bool mfma_ok(const sv_state *h, int k, int prec) {
     if (prec == SV_PREC_NATIVE || h->dtype != SV_C64 || (k != 4 && k != 5)) return false;
@@ -751,19 +779,22 @@ struct FusedPass {
     TileSpec sp{};
     int m = 0;
     int k = 0;
-    bool mfma = false;
+    int engine = SV_PREC_NATIVE;
     std::vector<DenseBlock> blocks;
     std::vector<std::vector<std::complex<double>>> mats;
 };
 
-static size_t dense_op_bytes(const sv_state *h, int k, bool mfma, int prec) {
-    if (mfma) return align256(frag_bytes(k, prec));
+// engine: the launch_dense_pass precision code of a pass (SV_PREC_NATIVE =
+// vector ALUs, SV_PREC_FP32 / SV_PREC_SPLIT_BF16 = complex64 matrix cores,
+// kPrecMfma64 = complex128 on the FP64 matrix cores).
+static size_t dense_op_bytes(const sv_state *h, int k, int engine) {
+    if (engine == kPrecMfma64) return align256(frag64_bytes(k));
+    if (engine != SV_PREC_NATIVE) return align256(frag_bytes(k, engine));
     return align256(((size_t)1 << (2 * k)) * (h->dtype == SV_C64 ? 8 : 16));
 }
 
-static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp, int prec) {
-    return align256(fp.blocks.size() * sizeof(DenseBlock)) +
-           fp.blocks.size() * dense_op_bytes(h, fp.k, fp.mfma, prec);
+static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp) {
+    return align256(fp.blocks.size() * sizeof(DenseBlock)) + fp.blocks.size() * dense_op_bytes(h, fp.k, fp.engine);
 }
 
 // Embed a k-qubit matrix in K qubits (extra index bits k..K-1 act as identity).
@@ -797,8 +828,17 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
         }
         tile_layout(h->n, mmax, lmin, needed, &fp.sp);
         fp.m = fp.sp.L + fp.sp.K;
-        fp.mfma = prec != SV_PREC_NATIVE && mfma_ok(h, std::max(4, kmax), prec);
-        fp.k = fp.mfma ? std::max(4, kmax) : kmax;
+        // blocks run on the matrix cores in the requested precision (the
+        // state's own for SV_PREC_NATIVE) whenever the tile holds whole
+        // wave-tiles; narrower blocks are padded to 4 qubits for that
+        const int K = std::max(4, kmax);
+        if (h->dtype == SV_C64) {
+            const int p32 = prec == SV_PREC_NATIVE ? SV_PREC_FP32 : prec;
+            fp.engine = mfma_ok(h, K, p32) ? p32 : SV_PREC_NATIVE;
+        } else {
+            fp.engine = mfma64_ok(h, K) ? kPrecMfma64 : SV_PREC_NATIVE;
+        }
+        fp.k = fp.engine == SV_PREC_NATIVE ? kmax : K;
         for (int bi : p.gates) {
             const Block &B = bs[bi];
             DenseBlock db{};
@@ -827,15 +867,17 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
 
 // Write a fused pass (block records, then one operand per block) at 'off';
 // operand offsets are relative to the arena base.
-static void stage_fused(sv_state *h, FusedPass &fp, int prec, size_t off) {
-    const size_t ob = dense_op_bytes(h, fp.k, fp.mfma, prec);
+static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
+    const size_t ob = dense_op_bytes(h, fp.k, fp.engine);
     size_t opo = off + align256(fp.blocks.size() * sizeof(DenseBlock));
     for (size_t b = 0; b < fp.blocks.size(); ++b, opo += ob) {
         fp.blocks[b].op_off = (int64_t)opo;
         char *dst = h->h_arena + opo;
         const std::complex<double> *U = fp.mats[b].data();
-        if (fp.mfma) {
-            make_fragments(U, fp.k, prec, dst);
+        if (fp.engine == kPrecMfma64) {
+            make_fragments64(U, fp.k, dst);
+        } else if (fp.engine != SV_PREC_NATIVE) {
+            make_fragments(U, fp.k, fp.engine, dst);
         } else if (h->dtype == SV_C64) {
             float *f = reinterpret_cast<float *>(dst);
             for (size_t i = 0; i < fp.mats[b].size(); ++i) {
@@ -853,29 +895,29 @@ static void stage_fused(sv_state *h, FusedPass &fp, int prec, size_t off) {
     std::memcpy(h->h_arena + off, fp.blocks.data(), fp.blocks.size() * sizeof(DenseBlock));
 }
 
-static int launch_fused(sv_state *h, const FusedPass &fp, int prec, size_t off) {
+static int launch_fused(sv_state *h, const FusedPass &fp, size_t off) {
     Timed tm(h, K_FUSED, 2.0 * state_bytes(h));
     SV_HIP(launch_dense_pass(h->amps, h->n, h->dtype, fp.sp, fp.k,
                              reinterpret_cast<const DenseBlock *>(h->d_arena + off), (int)fp.blocks.size(),
-                             h->d_arena, fp.mfma ? prec : SV_PREC_NATIVE, h->stream));
+                             h->d_arena, fp.engine, h->stream));
     return SV_OK;
 }
 
 // Stage, upload and launch a sequence of fused passes.
-static int run_fused_passes(sv_state *h, std::vector<FusedPass> &fps, int prec) {
+static int run_fused_passes(sv_state *h, std::vector<FusedPass> &fps) {
     std::vector<size_t> offs(fps.size());
     size_t total = 0;
     for (size_t i = 0; i < fps.size(); ++i) {
         offs[i] = total;
-        total += align256(fused_pass_bytes(h, fps[i], prec));
+        total += align256(fused_pass_bytes(h, fps[i]));
     }
     int rc = ensure_arena(h, total);
     if (rc) return rc;
     if ((rc = stage_wait(h))) return rc;
-    for (size_t i = 0; i < fps.size(); ++i) stage_fused(h, fps[i], prec, offs[i]);
+    for (size_t i = 0; i < fps.size(); ++i) stage_fused(h, fps[i], offs[i]);
     if ((rc = upload_arena(h, total))) return rc;
     for (size_t i = 0; i < fps.size(); ++i)
-        if ((rc = launch_fused(h, fps[i], prec, offs[i]))) return rc;
+        if ((rc = launch_fused(h, fps[i], offs[i]))) return rc;
     return SV_OK;
 }
 
@@ -1335,15 +1377,15 @@ int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int p
     const int D = 1 << k;
     for (int i = 0; i < 2 * D * D; ++i)
         if (!std::isfinite(U[i])) return fail(SV_EINVAL, "matrix entry is not finite");
-    if (prec != SV_PREC_NATIVE && (h->dtype != SV_C64 || k < 4))
-        return fail(SV_EUNSUPPORTED, "matrix-core blocks need a complex64 state and k >= 4");
+    if (prec != SV_PREC_NATIVE && h->dtype != SV_C64)
+        return fail(SV_EUNSUPPORTED, "FP32 and split-BF16 blocks need a complex64 state");
     Block B;
     B.k = k;
     for (int j = 0; j < k; ++j) B.q[j] = qubits[j];
     B.M.resize((size_t)D * D);
     for (int i = 0; i < D * D; ++i) B.M[i] = {U[2 * i], U[2 * i + 1]};
     std::vector<FusedPass> fps = compile_fused(h, std::vector<Block>{B}, prec);
-    return run_fused_passes(h, fps, prec);
+    return run_fused_passes(h, fps);
 }
 
 int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int n_params,
@@ -1392,7 +1434,7 @@ int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params,
             return fail(SV_EINVAL, "a gate touches more qubits than k_max");
     std::vector<Block> bs = fuse(gs, kk);
     std::vector<FusedPass> fps = compile_fused(h, bs, prec);
-    if ((rc = run_fused_passes(h, fps, prec))) return rc;
+    if ((rc = run_fused_passes(h, fps))) return rc;
     if (n_blocks_out) *n_blocks_out = (int)bs.size();
     return SV_OK;
 }

@@ -137,6 +137,8 @@ struct DenseBlock {
     int32_t pad;
     int64_t op_off;
 };
+// launch_dense_pass precision code for complex128 blocks on the FP64 matrix cores
+constexpr int kPrecMfma64 = 100;
 hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, int k,
                              const DenseBlock *dev_blocks, int n_blocks, const char *dev_base, int prec,
                              hipStream_t s);
