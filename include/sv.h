@@ -174,8 +174,11 @@ int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int
             int k_max, int max_blocks, int *block_k, int *block_qubits, double *block_mats,
             int *block_gates, int *n_blocks);
 
-/* Fuse (as sv_fuse) and apply every block with sv_apply_fused(prec); blocks
- * of fewer than 4 qubits use the native path.  *n_blocks_out (may be NULL)
+/* Apply the gate list through fused tile passes: the gates are first grouped
+ * into passes whose qubits (targets and controls) fit one LDS tile, then the
+ * gates of each pass are fused as by sv_fuse into blocks of at most k_max
+ * qubits, and every block of a pass is applied, as by sv_apply_fused(prec),
+ * during a single read and write of the state.  *n_blocks_out (may be NULL)
  * receives the number of blocks applied. */
 int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
                  int k_max, int prec, int *n_blocks_out);

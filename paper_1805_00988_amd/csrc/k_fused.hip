@@ -146,203 +146,231 @@ __global__ __launch_bounds__(256) void k_dense_native(typename V16<T>::type *v, 
     }
 }
 
-// ---------------------------------------------------- MFMA, complex64
-// Per-lane B-operand fragments, laid out by the host:
-//   FP32:       frag[(part * KSTEPS + s) * 64 + lane]            (float)
-//   split-BF16: frag[((part * KSTEPS + s) * 2 + hl) * 64 + lane]  (bf16x8)
-// part 0 -> Re Y, part 1 -> Im Y; hl 0 = hi, 1 = lo.
-template <int K, int PREC>
-struct MfmaShape;
-// K = 5, FP32: 32x32x2, 32 K-steps over [Re x | Im x] (64)
-template <>
-struct MfmaShape<5, 1> {
-    static constexpr int rows = 32, ksteps = 32;
-};
-// K = 4, FP32: 16x16x4, 8 K-steps over 32
-template <>
-struct MfmaShape<4, 1> {
-    static constexpr int rows = 16, ksteps = 8;
-};
-// K = 5, BF16: 32x32x16, 4 K-steps over 64
-template <>
-struct MfmaShape<5, 2> {
-    static constexpr int rows = 32, ksteps = 4;
-};
-// K = 4, BF16: 16x16x32, 1 K-step over 32
-template <>
-struct MfmaShape<4, 2> {
-    static constexpr int rows = 16, ksteps = 1;
-};
+// ------------------------------------------------------------ matrix cores
+// All matrix-core kernels share one addressing scheme.  A wave-tile is ROWS
+// groups (MFMA rows) of one block; the group index of row i of wave-tile wt
+// is wt*ROWS + i, and its LDS offset is goff[wt*ROWS] ^ goff[i] since the two
+// parts have disjoint bits.  So every A-operand and result address is a
+// per-lane constant (set once per block) XOR a wave-uniform table entry,
+// read through the scalar cache.
+//
+// Operand fragments (host-built, per lane, in the MFMA B-operand order):
+//   split-BF16: frag[((part * KS + s) * 2 + hl) * 64 + lane]   (bf16x8)
+//   FP32:       frag[(part * KS + s) * 64 + lane]               (float)
+//   FP64:       frag[((part * NT + nt) * KS + s) * 64 + lane]   (double)
+// part 0 -> Re Y, part 1 -> Im Y; hl 0 = hi, 1 = lo.  Split-BF16 orders the
+// real K index as (amplitude, re/im) interleaved, so a lane's 8 operand
+// elements are the real and imaginary parts of 4 amplitudes; FP32 and FP64
+// order it [Re x | Im x].
 
 // x ~ hi + lo with hi = bf16(x) and lo = bf16(x - hi)
 __device__ __forceinline__ __bf16 bf16_hi(float x) { return (__bf16)x; }
 __device__ __forceinline__ __bf16 bf16_lo(float x, __bf16 hi) { return (__bf16)(x - (float)hi); }
 
-template <int K, int PREC>
-__global__ __launch_bounds__(kFuseThreads) void k_dense_mfma(float4 *v, TileSpec sp, int m,
-                                                             const DenseBlock *__restrict__ blocks,
-                                                             int n_blocks, const char *__restrict__ base_ptr,
-                                                             uint64_t n_tiles) {
-    using S = MfmaShape<K, PREC>;
-    constexpr int D = 1 << K;         // amplitudes per group = output columns
-    constexpr int ROWS = S::rows;     // groups per wave-tile
-    constexpr int KS = S::ksteps;
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Split-BF16 operands of 4 amplitudes (elements 2i, 2i+1 = re, im of x_i).
+__device__ __forceinline__ void split4(const cpx<float> (&x)[4], bf16x8 &h, bf16x8 &l) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const __bf16 a = bf16_hi(x[i].re), c = bf16_hi(x[i].im);
+        h[2 * i] = a;
+        h[2 * i + 1] = c;
+        l[2 * i] = bf16_lo(x[i].re, a);
+        l[2 * i + 1] = bf16_lo(x[i].im, c);
+    }
+}
+
+// complex64, split-BF16 (3 products, FP32 accumulate).  K = 4: 16x16x32,
+// one K-step; K = 5: 32x32x16, four K-steps.  Threads: 512 (K = 4), 256 (K = 5).
+template <int K>
+struct Bf16Cfg;
+template <>
+struct Bf16Cfg<4> {
+    static constexpr int rows = 16, ksteps = 1, threads = 512;
+};
+template <>
+struct Bf16Cfg<5> {
+    static constexpr int rows = 32, ksteps = 4, threads = 256;
+};
+
+template <int K>
+__global__ __launch_bounds__(Bf16Cfg<K>::threads) void k_dense_bf16(float4 *v, TileSpec sp, int m,
+                                                                    const DenseBlock *__restrict__ blocks,
+                                                                    int n_blocks, const char *__restrict__ base_ptr,
+                                                                    uint64_t n_tiles) {
+    using C = Bf16Cfg<K>;
+    constexpr int D = 1 << K, ROWS = C::rows, KS = C::ksteps;
     constexpr int ACC = ROWS == 32 ? 16 : 4;
     using accT = typename std::conditional<ROWS == 32, floatx16, floatx4>::type;
     extern __shared__ char lds_raw[];
     cpx<float> *lds = reinterpret_cast<cpx<float> *>(lds_raw);
     const uint32_t tsize = 1u << m;
-    const uint32_t n_groups = tsize >> K;
-    const uint32_t n_wt = n_groups / ROWS;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t n_wt = (tsize >> K) / ROWS;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int nwaves = blockDim.x >> 6;
-    const int r = lane % ROWS;          // A row (group within wave-tile) / D column (output amp)
-    const int kk = lane / ROWS;         // K sub-index of the lane
-
+    const int r = lane % ROWS, kk = lane / ROWS;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
         stage_in<float>(v, lds, sp, base, tsize);
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
-        const DenseBlock &B = blocks[b];
-        const BlockPos &bp = B.bp;
-        const void *frag = base_ptr + B.op_off;
-        // this block's B fragments in registers (the same for every group)
-        float bf32[2][PREC == 1 ? KS : 1];
-        bf16x8 bbf[2][PREC == 2 ? KS : 1][2];
-        if constexpr (PREC == 1) {
-            const float *f = reinterpret_cast<const float *>(frag);
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int s = 0; s < KS; ++s) bf32[p][s] = f[(p * KS + s) * 64 + lane];
-        } else {
-            const bf16x8 *f = reinterpret_cast<const bf16x8 *>(frag);
+            const DenseBlock &B = blocks[b];
+            const uint32_t *__restrict__ qoff = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
+            const uint32_t *__restrict__ goff = qoff + D;
+            const bf16x8 *f = reinterpret_cast<const bf16x8 *>(base_ptr + B.op_off);
+            bf16x8 bw[2][KS][2];
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
 #pragma unroll
-                    for (int hl = 0; hl < 2; ++hl) bbf[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
-        }
-        // Addresses: A element j of group row, and output (row, col), are
-        // XORs of swizzled deposits of disjoint index parts (see above).
-        auto PQ = [&](uint32_t j) { return lds_phys<float>(deposit(j, bp.qpos, K)); };
-        auto PG = [&](uint32_t g) { return lds_phys<float>(deposit(g, bp.gpos, bp.ng)); };
-        const uint32_t pcol = PQ((uint32_t)r);           // this lane's output amplitude
-        const uint32_t prow_lane = PG((uint32_t)r);      // this lane's A row
-        const uint32_t pout_lane = PG(ROWS == 32 ? 4u * kk : 4u * kk) ^ pcol;
-        // per-lane part of the A amplitude index
-        const uint32_t pa_lane = PREC == 1 ? PQ((uint32_t)kk) : PQ(ROWS == 32 ? 8u * kk : 8u * (kk & 1));
-        for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-            const uint32_t pgw = PG(wt * ROWS);
-            const uint32_t arow = pgw ^ prow_lane ^ pa_lane;
-            accT yr = {}, yi = {};
-            if constexpr (PREC == 1) {
-                constexpr int half = KS / 2;
-                constexpr int per = ROWS == 32 ? 2 : 4; // K per MFMA
+                    for (int hl = 0; hl < 2; ++hl) bw[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
+            // lane (r, kk) reads amplitudes 8s + 4kk + i of row r; holds result
+            // rows 4kk + q (16x16) or 8(q/4) + 4kk + q%4 (32x32) of column r
+            const uint32_t a_lane = goff[r] ^ qoff[4 * kk];
+            const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
+            for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
+                const uint32_t gw = goff[wt * ROWS];
+                const uint32_t pa = gw ^ a_lane;
+                accT yr = {}, yi = {};
 #pragma unroll
-                for (int s = 0; s < half; ++s) {
-                    const cpx<float> x = lds[arow ^ PQ((uint32_t)(per * s))];
+                for (int s = 0; s < KS; ++s) {
+                    cpx<float> x[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) x[i] = lds[pa ^ qoff[8 * s + i]];
+                    bf16x8 h, l;
+                    split4(x, h, l);
                     if constexpr (ROWS == 32) {
-                        yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bf32[0][s], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bf32[1][s], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bf32[0][s + half], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bf32[1][s + half], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][0], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][0], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][1], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][1], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[0][s][0], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[1][s][0], yi, 0, 0, 0);
                     } else {
-                        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bf32[0][s], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bf32[1][s], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bf32[0][s + half], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bf32[1][s + half], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][0], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][0], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][1], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][1], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[0][s][0], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[1][s][0], yi, 0, 0, 0);
                     }
                 }
-            } else {
-                if constexpr (ROWS == 32) {
-                    // K-step s < 2: Re of amps 16s + 8kk + e; s >= 2: Im of the same amps
+                const uint32_t po = gw ^ o_lane;
 #pragma unroll
-                    for (int s2 = 0; s2 < 2; ++s2) {
-                        bf16x8 rh, rl, ih, il;
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const cpx<float> x = lds[arow ^ PQ((uint32_t)(16 * s2 + e))];
-                            const __bf16 a = bf16_hi(x.re), c = bf16_hi(x.im);
-                            rh[e] = a;
-                            rl[e] = bf16_lo(x.re, a);
-                            ih[e] = c;
-                            il[e] = bf16_lo(x.im, c);
-                        }
-#pragma unroll
-                        for (int p = 0; p < 2; ++p) {
-                            accT &acc = p == 0 ? yr : yi;
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bbf[p][s2][0], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bbf[p][s2][1], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rl, bbf[p][s2][0], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bbf[p][s2 + 2][0], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bbf[p][s2 + 2][1], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(il, bbf[p][s2 + 2][0], acc, 0, 0, 0);
-                        }
-                    }
-                } else {
-                    // one K-step of 32: kk = 0,1 -> Re of amps 8kk + e; kk = 2,3 -> Im of amps 8(kk-2) + e
-                    bf16x8 ah, al;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const cpx<float> x = lds[arow ^ PQ((uint32_t)e)];
-                        const float c = kk < 2 ? x.re : x.im;
-                        const __bf16 a = bf16_hi(c);
-                        ah[e] = a;
-                        al[e] = bf16_lo(c, a);
-                    }
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        accT &acc = p == 0 ? yr : yi;
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bbf[p][0][0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bbf[p][0][1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bbf[p][0][0], acc, 0, 0, 0);
-                    }
+                for (int q = 0; q < ACC; ++q) {
+                    const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
+                    lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
                 }
             }
-            // D[row][col]: col = r (output amplitude), rows from the accumulator layout
-            const uint32_t pout = pgw ^ pout_lane;
-#pragma unroll
-            for (int q = 0; q < ACC; ++q) {
-                const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
-                lds[pout ^ PG(rq)] = cpx<float>{yr[q], yi[q]};
-            }
+            __syncthreads();
         }
-        __syncthreads();
-        } // blocks
         stage_out<float>(v, lds, sp, base, tsize);
         __syncthreads();
     }
-    (void)D;
 }
 
-
-// ---------------------------------------------------- MFMA, complex128
-// FP64 matrix cores (v_mfma_f64_16x16x4f64, operands laid out as the FP32
-// 16x16x4 one; result element q of lane l is row 4q + l/16, column l%16, as
-// measured on the device): wave-tiles of 16 groups; K
-// index 4s + kk of [Re x | Im x] (lane kk = lane / 16 loads amplitude
-// 4s + kk and uses its real part at K-step s, its imaginary part at K-step
-// s + D/4); D/16 output tiles of 16 amplitudes per part.  Operand fragments:
-// frag[((part * NT + nt) * KS + s) * 64 + lane] (double), kept in registers
-// for k = 4 and read from L1 per K-step for k = 5.
+// complex64, FP32 (v_mfma_f32_16x16x4_f32 for K = 4, 32x32x2 for K = 5).
+// K-step s uses element s*KPS + kk of [Re x | Im x]: the lane loads
+// amplitude KPS*s + kk once and uses its real part at step s and its
+// imaginary part at step s + KS/2.
 template <int K>
-__global__ __launch_bounds__(kFuseThreads) void k_dense_mfma64(double2 *v, TileSpec sp, int m,
-                                                               const DenseBlock *__restrict__ blocks,
-                                                               int n_blocks, const char *__restrict__ base_ptr,
-                                                               uint64_t n_tiles) {
+struct F32Cfg;
+template <>
+struct F32Cfg<4> {
+    static constexpr int rows = 16, kps = 4, threads = 512;
+};
+template <>
+struct F32Cfg<5> {
+    static constexpr int rows = 32, kps = 2, threads = 256;
+};
+
+template <int K>
+__global__ __launch_bounds__(F32Cfg<K>::threads) void k_dense_f32(float4 *v, TileSpec sp, int m,
+                                                                  const DenseBlock *__restrict__ blocks,
+                                                                  int n_blocks, const char *__restrict__ base_ptr,
+                                                                  uint64_t n_tiles) {
+    using C = F32Cfg<K>;
+    constexpr int D = 1 << K, ROWS = C::rows, KPS = C::kps;
+    constexpr int KS = 2 * D / KPS, HALF = KS / 2;
+    constexpr int ACC = ROWS == 32 ? 16 : 4;
+    using accT = typename std::conditional<ROWS == 32, floatx16, floatx4>::type;
+    extern __shared__ char lds_raw[];
+    cpx<float> *lds = reinterpret_cast<cpx<float> *>(lds_raw);
+    const uint32_t tsize = 1u << m;
+    const uint32_t n_wt = (tsize >> K) / ROWS;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int nwaves = blockDim.x >> 6;
+    const int r = lane % ROWS, kk = lane / ROWS;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t base = tile_base(sp, tile);
+        stage_in<float>(v, lds, sp, base, tsize);
+        __syncthreads();
+        for (int b = 0; b < n_blocks; ++b) {
+            const DenseBlock &B = blocks[b];
+            const uint32_t *__restrict__ qoff = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
+            const uint32_t *__restrict__ goff = qoff + D;
+            const float *f = reinterpret_cast<const float *>(base_ptr + B.op_off);
+            float bw[2][KS];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int s = 0; s < KS; ++s) bw[p][s] = f[(p * KS + s) * 64 + lane];
+            const uint32_t a_lane = goff[r] ^ qoff[kk];
+            const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
+            for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
+                const uint32_t gw = goff[wt * ROWS];
+                const uint32_t pa = gw ^ a_lane;
+                accT yr = {}, yi = {};
+#pragma unroll
+                for (int s = 0; s < HALF; ++s) {
+                    const cpx<float> x = lds[pa ^ qoff[KPS * s]];
+                    if constexpr (ROWS == 32) {
+                        yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[0][s], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[1][s], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
+                    } else {
+                        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[0][s], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[1][s], yi, 0, 0, 0);
+                        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
+                        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
+                    }
+                }
+                const uint32_t po = gw ^ o_lane;
+#pragma unroll
+                for (int q = 0; q < ACC; ++q) {
+                    const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
+                    lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
+                }
+            }
+            __syncthreads();
+        }
+        stage_out<float>(v, lds, sp, base, tsize);
+        __syncthreads();
+    }
+}
+
+// complex128 on the FP64 matrix cores (v_mfma_f64_16x16x4f64; operands laid
+// out as the FP32 16x16x4 ones, result element q of lane l is row 4q + l/16,
+// column l%16, as measured on the device): wave-tiles of 16 groups, D/16
+// output tiles of 16 amplitudes per part, K-steps as in the FP32 kernel.
+// Fragments stay in registers for K = 4 and are read per K-step (L1) for K = 5.
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_f64(double2 *v, TileSpec sp, int m,
+                                                   const DenseBlock *__restrict__ blocks, int n_blocks,
+                                                   const char *__restrict__ base_ptr, uint64_t n_tiles) {
     constexpr int D = 1 << K;
-    constexpr int NT = D / 16;     // output tiles per part
-    constexpr int KS = 2 * D / 4;  // K-steps over 2D
+    constexpr int NT = D / 16;
+    constexpr int KS = 2 * D / 4;
     constexpr int HALF = KS / 2;
     constexpr bool PRELOAD = K == 4;
     extern __shared__ char lds_raw[];
     cpx<double> *lds = reinterpret_cast<cpx<double> *>(lds_raw);
     const uint32_t tsize = 1u << m;
     const uint32_t n_wt = (tsize >> K) / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int nwaves = blockDim.x >> 6;
     const int r = lane & 15, kk = lane >> 4;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -351,21 +379,19 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma64(double2 *v, TileS
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
-            const BlockPos &bp = B.bp;
+            const uint32_t *__restrict__ qoff = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
+            const uint32_t *__restrict__ goff = qoff + D;
             const double *frag = reinterpret_cast<const double *>(base_ptr + B.op_off);
             double bpre[PRELOAD ? 2 * NT * KS : 1];
             if constexpr (PRELOAD) {
 #pragma unroll
                 for (int i = 0; i < 2 * NT * KS; ++i) bpre[i] = frag[i * 64 + lane];
             }
-            auto PQ = [&](uint32_t j) { return lds_phys<double>(deposit(j, bp.qpos, K)); };
-            auto PG = [&](uint32_t g) { return lds_phys<double>(deposit(g, bp.gpos, bp.ng)); };
-            const uint32_t lane_a = PG((uint32_t)r) ^ PQ((uint32_t)kk);
-            // FP64 16x16x4 result layout: element q of lane (r, kk) is row 4q + kk
-            const uint32_t lane_out = PG((uint32_t)kk) ^ PQ((uint32_t)r);
+            const uint32_t a_lane = goff[r] ^ qoff[kk];
+            const uint32_t o_lane = goff[kk] ^ qoff[r];
             for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-                const uint32_t pgw = PG(wt * 16u);
-                const uint32_t arow = pgw ^ lane_a;
+                const uint32_t gw = goff[wt * 16u];
+                const uint32_t pa = gw ^ a_lane;
                 doublex4 acc[2][NT];
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
@@ -373,7 +399,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma64(double2 *v, TileS
                     for (int nt = 0; nt < NT; ++nt) acc[p][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int s = 0; s < HALF; ++s) {
-                    const cpx<double> x = lds[arow ^ PQ((uint32_t)(4 * s))];
+                    const cpx<double> x = lds[pa ^ qoff[4 * s]];
 #pragma unroll
                     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -385,14 +411,12 @@ __global__ __launch_bounds__(kFuseThreads) void k_dense_mfma64(double2 *v, TileS
                             acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, b1, acc[p][nt], 0, 0, 0);
                         }
                 }
-                // D: lane holds rows 4q + kk of output tile nt, column r
-                const uint32_t pout = pgw ^ lane_out;
+                const uint32_t po = gw ^ o_lane;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        lds[pout ^ PG(4u * q) ^ PQ((uint32_t)(16 * nt))] =
-                            cpx<double>{acc[0][nt][q], acc[1][nt][q]};
+                        lds[po ^ goff[4 * q] ^ qoff[16 * nt]] = cpx<double>{acc[0][nt][q], acc[1][nt][q]};
             }
             __syncthreads();
         }
@@ -415,15 +439,13 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
     if (prec == kPrecMfma64) {
         if (dtype != SV_C128 || k < 4 || ((1u << m) >> k) % 16) return hipErrorInvalidValue;
         if (k == 4) {
-            (void)hipFuncSetAttribute((const void *)k_dense_mfma64<4>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            k_dense_mfma64<4><<<grid, kFuseThreads, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks,
-                                                              dev_base, n_tiles);
+            (void)hipFuncSetAttribute((const void *)k_dense_f64<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            k_dense_f64<4><<<grid, 256, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks, dev_base, n_tiles);
         } else {
-            (void)hipFuncSetAttribute((const void *)k_dense_mfma64<5>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            k_dense_mfma64<5><<<grid, kFuseThreads, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks,
-                                                              dev_base, n_tiles);
+            (void)hipFuncSetAttribute((const void *)k_dense_f64<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            k_dense_f64<5><<<grid, 256, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks, dev_base, n_tiles);
         }
         return hipGetLastError();
     }
@@ -431,18 +453,18 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
         if (dtype != SV_C64 || k < 4) return hipErrorInvalidValue;
         const int rows = k == 5 ? 32 : 16;
         if (((1u << m) >> k) % rows) return hipErrorInvalidValue; // whole wave-tiles only
-#define SV_MFMA_CASE(KK, PP)                                                                       \
-    if (k == KK && prec == PP) {                                                                   \
-        (void)hipFuncSetAttribute((const void *)k_dense_mfma<KK, PP>,                              \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
-        k_dense_mfma<KK, PP><<<grid, kFuseThreads, lds, s>>>((float4 *)amps, sp, m, dev_blocks,    \
-                                                             n_blocks, dev_base, n_tiles);         \
+#define SV_MFMA_CASE(KERN, KK, THREADS)                                                            \
+    {                                                                                              \
+        (void)hipFuncSetAttribute((const void *)KERN<KK>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                  (int)lds);                                                       \
+        KERN<KK><<<grid, THREADS, lds, s>>>((float4 *)amps, sp, m, dev_blocks, n_blocks, dev_base,  \
+                                            n_tiles);                                              \
         return hipGetLastError();                                                                  \
     }
-        SV_MFMA_CASE(5, 1)
-        SV_MFMA_CASE(4, 1)
-        SV_MFMA_CASE(5, 2)
-        SV_MFMA_CASE(4, 2)
+        if (prec == SV_PREC_SPLIT_BF16 && k == 4) SV_MFMA_CASE(k_dense_bf16, 4, Bf16Cfg<4>::threads)
+        if (prec == SV_PREC_SPLIT_BF16 && k == 5) SV_MFMA_CASE(k_dense_bf16, 5, Bf16Cfg<5>::threads)
+        if (prec == SV_PREC_FP32 && k == 4) SV_MFMA_CASE(k_dense_f32, 4, F32Cfg<4>::threads)
+        if (prec == SV_PREC_FP32 && k == 5) SV_MFMA_CASE(k_dense_f32, 5, F32Cfg<5>::threads)
 #undef SV_MFMA_CASE
         return hipErrorInvalidValue;
     }

@@ -708,7 +708,16 @@ static size_t frag_bytes(int k, int prec) {
     return (size_t)2 * (k == 5 ? 4 : 1) * 2 * 64 * 16;
 }
 
-// Lay out U in the per-lane order the MFMA kernel loads (see k_fused.hip).
+// Split-BF16 orders the K rows (amplitude, re/im) interleaved: row 2a + c
+// multiplies component c of amplitude a.
+static float bpart_interleaved(const std::complex<double> *U, int D, int part, int krow, int col) {
+    const std::complex<double> u = U[(size_t)col * D + (krow >> 1)];
+    const bool re = (krow & 1) == 0;
+    if (part == 0) return (float)(re ? u.real() : -u.imag());
+    return (float)(re ? u.imag() : u.real());
+}
+
+// Lay out U in the per-lane order the MFMA kernels load (see k_fused.hip).
 static void make_fragments(const std::complex<double> *U, int k, int prec, char *out) {
     const int D = 1 << k;
     if (prec == SV_PREC_FP32) {
@@ -726,8 +735,8 @@ static void make_fragments(const std::complex<double> *U, int k, int prec, char 
             for (int st = 0; st < KS; ++st)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int e = 0; e < 8; ++e) {
-                        const int krow = k == 5 ? 16 * st + 8 * (lane / rows) + e : 8 * (lane / rows) + e;
-                        const float x = bpart(U, D, p, krow, lane % rows);
+                        const int krow = (512 / rows) * st + 8 * (lane / rows) + e;
+                        const float x = bpart_interleaved(U, D, p, krow, lane % rows);
                         const uint16_t hi = bf16_bits(x);
                         const uint16_t lo = bf16_bits(x - bf16_value(hi));
                         f[(((p * KS + st) * 2 + 0) * 64 + lane) * 8 + e] = hi;
@@ -787,14 +796,24 @@ struct FusedPass {
 // engine: the launch_dense_pass precision code of a pass (SV_PREC_NATIVE =
 // vector ALUs, SV_PREC_FP32 / SV_PREC_SPLIT_BF16 = complex64 matrix cores,
 // kPrecMfma64 = complex128 on the FP64 matrix cores).
-static size_t dense_op_bytes(const sv_state *h, int k, int engine) {
+static bool is_mfma(int engine) { return engine != SV_PREC_NATIVE; }
+
+static size_t dense_frag_bytes(const sv_state *h, int k, int engine) {
     if (engine == kPrecMfma64) return align256(frag64_bytes(k));
     if (engine != SV_PREC_NATIVE) return align256(frag_bytes(k, engine));
     return align256(((size_t)1 << (2 * k)) * (h->dtype == SV_C64 ? 8 : 16));
 }
 
+// operand plus, for the matrix cores, the LDS offset tables (qoff, goff)
+static size_t dense_op_bytes(const sv_state *h, int k, int m, int engine) {
+    size_t b = dense_frag_bytes(h, k, engine);
+    if (is_mfma(engine)) b += align256((((size_t)1 << k) + ((size_t)1 << (m - k))) * sizeof(uint32_t));
+    return b;
+}
+
 static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp) {
-    return align256(fp.blocks.size() * sizeof(DenseBlock)) + fp.blocks.size() * dense_op_bytes(h, fp.k, fp.engine);
+    return align256(fp.blocks.size() * sizeof(DenseBlock)) +
+           fp.blocks.size() * dense_op_bytes(h, fp.k, fp.m, fp.engine);
 }
 
 // Embed a k-qubit matrix in K qubits (extra index bits k..K-1 act as identity).
@@ -807,60 +826,91 @@ static std::vector<std::complex<double>> pad_matrix(const std::vector<std::compl
     return P;
 }
 
-// Build the passes for a list of blocks (each: qubits q[0..k-1], matrix M).
+// Shortest contiguous run (low tile qubits) of a fused pass: 1 KiB.
+static int fused_lmin(const sv_state *h) { return std::min(h->n, h->dtype == SV_C64 ? 7 : 6); }
+
+// One fused pass over the blocks bs[idx] (all their qubits fit in one tile).
+// Blocks run on the matrix cores in the requested precision (the state's own
+// for SV_PREC_NATIVE) whenever the tile holds whole wave-tiles; narrower
+// blocks are then padded to 4 qubits.
+static FusedPass build_fused_pass(const sv_state *h, const std::vector<Block> &bs, const std::vector<int> &idx,
+                                  int prec) {
+    const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
+    FusedPass fp;
+    uint64_t needed = 0;
+    int kmax = 0;
+    for (int bi : idx) {
+        for (int j = 0; j < bs[bi].k; ++j) needed |= 1ull << bs[bi].q[j];
+        kmax = std::max(kmax, bs[bi].k);
+    }
+    tile_layout(h->n, mmax, fused_lmin(h), needed, &fp.sp);
+    fp.m = fp.sp.L + fp.sp.K;
+    const int K = std::max(4, kmax);
+    if (h->dtype == SV_C64) {
+        const int p32 = prec == SV_PREC_NATIVE ? SV_PREC_FP32 : prec;
+        fp.engine = mfma_ok(h, K, p32) ? p32 : SV_PREC_NATIVE;
+    } else {
+        fp.engine = mfma64_ok(h, K) ? kPrecMfma64 : SV_PREC_NATIVE;
+    }
+    fp.k = fp.engine == SV_PREC_NATIVE ? kmax : K;
+    for (int bi : idx) {
+        const Block &B = bs[bi];
+        DenseBlock db{};
+        db.bp.k = fp.k;
+        uint32_t used = 0;
+        for (int j = 0; j < B.k; ++j) {
+            db.bp.qpos[j] = local_bit(fp.sp, B.q[j]);
+            used |= 1u << db.bp.qpos[j];
+        }
+        // padding qubits: the highest tile positions the block does not use
+        for (int j = B.k, pos = fp.m - 1; j < fp.k; ++j) {
+            while ((used >> pos) & 1u) --pos;
+            db.bp.qpos[j] = pos;
+            used |= 1u << pos;
+        }
+        db.bp.ng = 0;
+        for (int b = 0; b < fp.m; ++b)
+            if (!((used >> b) & 1u)) db.bp.gpos[db.bp.ng++] = b;
+        fp.blocks.push_back(db);
+        fp.mats.push_back(B.k == fp.k ? B.M : pad_matrix(B.M, B.k, fp.k));
+    }
+    return fp;
+}
+
+// Passes for a list of blocks (each: qubits q[0..k-1], matrix M), grouped
+// by the tile scheduler.
 static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector<Block> &bs, int prec) {
     const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
-    const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
     std::vector<uint64_t> tm(bs.size());
     for (size_t b = 0; b < bs.size(); ++b) {
         tm[b] = 0;
         for (int j = 0; j < bs[b].k; ++j) tm[b] |= 1ull << bs[b].q[j];
     }
-    std::vector<Pass> passes = schedule_masks(tm, tm, mmax, lmin);
     std::vector<FusedPass> out;
-    for (const Pass &p : passes) {
-        FusedPass fp;
-        uint64_t needed = 0;
-        int kmax = 0;
-        for (int bi : p.gates) {
-            needed |= tm[bi];
-            kmax = std::max(kmax, bs[bi].k);
-        }
-        tile_layout(h->n, mmax, lmin, needed, &fp.sp);
-        fp.m = fp.sp.L + fp.sp.K;
-        // blocks run on the matrix cores in the requested precision (the
-        // state's own for SV_PREC_NATIVE) whenever the tile holds whole
-        // wave-tiles; narrower blocks are padded to 4 qubits for that
-        const int K = std::max(4, kmax);
-        if (h->dtype == SV_C64) {
-            const int p32 = prec == SV_PREC_NATIVE ? SV_PREC_FP32 : prec;
-            fp.engine = mfma_ok(h, K, p32) ? p32 : SV_PREC_NATIVE;
-        } else {
-            fp.engine = mfma64_ok(h, K) ? kPrecMfma64 : SV_PREC_NATIVE;
-        }
-        fp.k = fp.engine == SV_PREC_NATIVE ? kmax : K;
-        for (int bi : p.gates) {
-            const Block &B = bs[bi];
-            DenseBlock db{};
-            db.bp.k = fp.k;
-            uint32_t used = 0;
-            for (int j = 0; j < B.k; ++j) {
-                db.bp.qpos[j] = local_bit(fp.sp, B.q[j]);
-                used |= 1u << db.bp.qpos[j];
-            }
-            // padding qubits: the highest tile positions the block does not use
-            for (int j = B.k, pos = fp.m - 1; j < fp.k; ++j) {
-                while ((used >> pos) & 1u) --pos;
-                db.bp.qpos[j] = pos;
-                used |= 1u << pos;
-            }
-            db.bp.ng = 0;
-            for (int b = 0; b < fp.m; ++b)
-                if (!((used >> b) & 1u)) db.bp.gpos[db.bp.ng++] = b;
-            fp.blocks.push_back(db);
-            fp.mats.push_back(B.k == fp.k ? B.M : pad_matrix(B.M, B.k, fp.k));
-        }
-        out.push_back(std::move(fp));
+    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h))) out.push_back(build_fused_pass(h, bs, p.gates, prec));
+    return out;
+}
+
+// Tile-aware fusion of a gate list: the tile scheduler first groups the
+// gates into passes (every qubit of a gate, controls included, in the
+// tile), then each pass's gates are fused into blocks of at most k_max
+// qubits, so all blocks of a pass share one trip of the state through LDS.
+static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::vector<Gate> &gs, int k_max,
+                                                  int prec, int *n_blocks) {
+    const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
+    std::vector<uint64_t> qm(gs.size());
+    for (size_t i = 0; i < gs.size(); ++i) qm[i] = gs[i].qmask();
+    std::vector<FusedPass> out;
+    *n_blocks = 0;
+    for (const Pass &p : schedule_masks(qm, qm, mmax, fused_lmin(h))) {
+        std::vector<Gate> sub;
+        sub.reserve(p.gates.size());
+        for (int gi : p.gates) sub.push_back(gs[gi]);
+        const std::vector<Block> bs = fuse(sub, k_max);
+        std::vector<int> idx(bs.size());
+        for (size_t b = 0; b < bs.size(); ++b) idx[b] = (int)b;
+        out.push_back(build_fused_pass(h, bs, idx, prec));
+        *n_blocks += (int)bs.size();
     }
     return out;
 }
@@ -868,10 +918,14 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
 // Write a fused pass (block records, then one operand per block) at 'off';
 // operand offsets are relative to the arena base.
 static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
-    const size_t ob = dense_op_bytes(h, fp.k, fp.engine);
+    const size_t fb = dense_frag_bytes(h, fp.k, fp.engine);
+    const size_t ob = dense_op_bytes(h, fp.k, fp.m, fp.engine);
+    const int sw = lds_swizzle_bits(h->dtype == SV_C64 ? 8 : 16);
     size_t opo = off + align256(fp.blocks.size() * sizeof(DenseBlock));
     for (size_t b = 0; b < fp.blocks.size(); ++b, opo += ob) {
-        fp.blocks[b].op_off = (int64_t)opo;
+        DenseBlock &db = fp.blocks[b];
+        db.op_off = (int64_t)opo;
+        db.tab_off = 0;
         char *dst = h->h_arena + opo;
         const std::complex<double> *U = fp.mats[b].data();
         if (fp.engine == kPrecMfma64) {
@@ -890,6 +944,20 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
                 d[2 * i] = U[i].real();
                 d[2 * i + 1] = U[i].imag();
             }
+        }
+        if (is_mfma(fp.engine)) {
+            db.tab_off = (int64_t)(opo + fb);
+            uint32_t *qoff = reinterpret_cast<uint32_t *>(h->h_arena + opo + fb);
+            uint32_t *goff = qoff + (1u << fp.k);
+            auto deposit = [](uint32_t x, const int *pos, int nb) {
+                uint32_t r = 0;
+                for (int i = 0; i < nb; ++i)
+                    if ((x >> i) & 1u) r |= 1u << pos[i];
+                return r;
+            };
+            for (uint32_t j = 0; j < (1u << fp.k); ++j) qoff[j] = lds_swizzle(deposit(j, db.bp.qpos, fp.k), sw);
+            for (uint32_t g = 0; g < (1u << (fp.m - fp.k)); ++g)
+                goff[g] = lds_swizzle(deposit(g, db.bp.gpos, db.bp.ng), sw);
         }
     }
     std::memcpy(h->h_arena + off, fp.blocks.data(), fp.blocks.size() * sizeof(DenseBlock));
@@ -1432,10 +1500,10 @@ int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params,
     for (const Gate &g : gs)
         if (__builtin_popcountll(g.qmask()) > kk)
             return fail(SV_EINVAL, "a gate touches more qubits than k_max");
-    std::vector<Block> bs = fuse(gs, kk);
-    std::vector<FusedPass> fps = compile_fused(h, bs, prec);
+    int nb = 0;
+    std::vector<FusedPass> fps = compile_fused_gates(h, gs, kk, prec, &nb);
     if ((rc = run_fused_passes(h, fps))) return rc;
-    if (n_blocks_out) *n_blocks_out = (int)bs.size();
+    if (n_blocks_out) *n_blocks_out = nb;
     return SV_OK;
 }
 

@@ -98,6 +98,15 @@ struct TileSweep {
     int32_t pad[3];
 };
 
+// LDS swizzle of a tile index: the low sw bits (one 128-byte LDS row of
+// amplitudes) are XOR-ed with a fold of the higher bits.  Linear over XOR.
+__host__ __device__ inline uint32_t lds_swizzle(uint32_t l, int sw) {
+    const uint32_t f = (l >> sw) ^ (l >> (2 * sw)) ^ (l >> (3 * sw));
+    return l ^ (f & ((1u << sw) - 1u));
+}
+// swizzle width for amplitudes of 'amp_bytes' bytes (8: complex64, 16: complex128)
+__host__ __device__ constexpr int lds_swizzle_bits(int amp_bytes) { return amp_bytes == 8 ? 4 : 3; }
+
 constexpr int kMaxTileHigh = 8; // extra tile qubits beyond the low block
 struct TileSpec {
     int L;                    // low qubits 0..L-1 are in the tile
@@ -132,10 +141,16 @@ struct BlockPos {
     int gpos[16];
     int ng;
 };
+// tab_off: byte offset of the block's LDS offset tables (matrix cores only):
+// uint32 qoff[2^k] = swizzled LDS offset of matrix index j deposited at
+// qpos, then goff[2^(m-k)] = the same for group index g deposited at gpos.
+// Both maps are linear over XOR, so the offset of (group g, index j) is
+// goff[g] ^ qoff[j] and tables of disjoint index parts combine by XOR.
 struct DenseBlock {
     BlockPos bp;
     int32_t pad;
     int64_t op_off;
+    int64_t tab_off;
 };
 // launch_dense_pass precision code for complex128 blocks on the FP64 matrix cores
 constexpr int kPrecMfma64 = 100;

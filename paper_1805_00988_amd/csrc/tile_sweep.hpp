@@ -21,9 +21,7 @@ namespace sv {
 
 template <typename T>
 __device__ __forceinline__ uint32_t lds_phys(uint32_t l) {
-    constexpr int SW = sizeof(T) == 4 ? 4 : 3;
-    const uint32_t f = (l >> SW) ^ (l >> (2 * SW)) ^ (l >> (3 * SW));
-    return l ^ (f & ((1u << SW) - 1u));
+    return lds_swizzle(l, lds_swizzle_bits(2 * sizeof(T)));
 }
 
 // Matrix entry i of a record, stored in the state's own precision.
