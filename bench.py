@@ -28,6 +28,62 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Vector-ALU peak for FP64 and for FP32 without packed-FP32 instructions (all
+# HIP code here is built with them disabled): 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flop (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+
+
+def sources_digest() -> str:
+    """SHA-1 over the HIP sources: counter figures taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_1805_00988_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (scaled by the copy-kernel factors) for kernel@register, if the counters
+    were taken on the current sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = sources_digest()
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 5 and not line.startswith("#") and parts[0] == kernel_key:
+                if parts[4] != digest:
+                    return None
+                return float(parts[1]) + float(parts[2])
+    return None
+
+
+def roofline_of(key: str, cnt: int, ms: float, by: float, fl: float) -> dict:
+    """Roofline of one kernel from its launches: the binding roof is the one
+    of the kernel's arithmetic intensity (algorithmic flops per algorithmic
+    byte) against the vector-ALU ridge; both views are reported."""
+    sec = ms * 1e-3 / cnt
+    gbs = (by / cnt) / sec / 1e9
+    tfl = (fl / cnt) / sec / 1e12
+    ridge = ALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ai = fl / by if by > 0 else 0.0
+    hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    alu = {"achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(tfl / ALU_PEAK_TFLOPS, 4)}
+    bound = "alu" if ai > ridge else "hbm"
+    tr = measured_traffic(key)
+    out = {"bound": bound, **(alu if bound == "alu" else hbm), "traffic": tr,
+           "kernel": key, "launches": cnt, "avg_launch_ms": round(ms / cnt, 4),
+           "algorithmic_bytes_per_launch": by / cnt, "algorithmic_flops_per_launch": fl / cnt,
+           "flop_per_byte": round(ai, 3), "ridge_flop_per_byte": round(ridge, 3),
+           "hbm_view": hbm, "alu_view": alu}
+    return out
 
 
 def parse_sizes(spec: str):
@@ -48,7 +104,8 @@ def read_stats(lib, handle):
     arr = (_lib.sv_kernel_stat * cap)()
     n = ctypes.c_int()
     _lib.check(lib.sv_timing_read(handle, arr, cap, ctypes.byref(n)))
-    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].bytes))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].bytes),
+                                   float(arr[i].flops))
             for i in range(n.value)}
 
 
@@ -91,8 +148,9 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
             prec = prec_c64 if r["dtype"] == "c64" else sv.SV_PREC_NATIVE
             _lib.check(lib.sv_set_basis(h, r["qft"].basis))
             blocks = 0
+            kmax = args.fuse_k if r["dtype"] == "c64" else min(args.fuse_k, 4)
             for key, c in (("ops_qft", r["qft"]), ("ops_rnd", r["rnd"])):
-                _lib.check(lib.sv_run_fused(h, sv._opptr(r[key]), len(c.gates), None, 0, args.fuse_k, prec,
+                _lib.check(lib.sv_run_fused(h, sv._opptr(r[key]), len(c.gates), None, 0, kmax, prec,
                                             ctypes.byref(nb)))
                 blocks += nb.value
             _lib.check(lib.sv_probabilities(h, ctypes.c_void_p(r["probs"].data_ptr()), ctypes.byref(norm)))
@@ -108,7 +166,8 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
         print(f"# fused step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = {"prec_complex64": args.fused_prec, "prec_complex128": "fp64 vector", "k_max": args.fuse_k,
+    out = {"workload": "the same QFT + random circuit, fused", "prec_complex64": args.fused_prec,
+           "prec_complex128": "fp64 matrix cores", "k_max": args.fuse_k, "k_max_complex128": min(args.fuse_k, 4),
            "ms_per_step": dt / args.steps * 1e3, "registers": {}}
     total = 0
     for r in regs:
@@ -124,7 +183,7 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
             nb2 += float(torch.vdot(bc, bc).real.item())
         fid = abs(ov) ** 2 / (na * nb2)
         total += r["updates"]
-        fk = per.get("fused_block", (1, 0.0, 0.0))
+        fk = per.get("fused_block", (1, 0.0, 0.0, 0.0))
         out["registers"][f"{r['n']}q_{r['dtype']}"] = {
             "blocks_per_step": r["fused_blocks"], "norm": r["fused_norm"],
             "fidelity_vs_plain": fid,
@@ -135,6 +194,75 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
     out["value"] = total * args.steps / dt
     out["unit"] = "updates/s"
     return out
+
+
+def compare_states(a, ref, torch):
+    """Fidelity |<ref|a>|^2 / (|ref|^2 |a|^2) and max |a - ref| over chunks
+    (a may be complex64; every chunk is promoted to complex128)."""
+    ov, na, nr, mx = 0j, 0.0, 0.0, 0.0
+    for c0 in range(0, a.numel(), 1 << 26):
+        x = a[c0:c0 + (1 << 26)].to(torch.complex128)
+        y = ref[c0:c0 + (1 << 26)]
+        ov += complex(torch.vdot(y, x).item())
+        na += float(torch.vdot(x, x).real.item())
+        nr += float(torch.vdot(y, y).real.item())
+        mx = max(mx, float((x - y).abs().max().item()))
+        del x
+    return abs(ov) ** 2 / (na * nr), mx
+
+
+def bench_fusion(n, seed, steps, warmup, torch):
+    """Fusion workload: n-qubit seeded random circuit of depth 40 (a random
+    one-qubit gate per qubit and n/2 CZ on random pairs per layer), complex64,
+    run plain (tile passes, one gate at a time) and fused (each tile pass's
+    gates fused into blocks of at most k = 4 or 5 qubits on the matrix cores,
+    FP32 or split-BF16).  Every variant's final state is compared with the
+    complex128 plain path on the same circuit."""
+    import circuits as C
+    import paper_1805_00988_amd as sv
+    from paper_1805_00988_amd import _lib
+
+    lib = _lib.load()
+    circ = C.config2(n=n, seed=seed, depth=40)
+    ops = sv.ops_from_gates(circ.gates)
+    ref = sv.State(n, "c128")
+    _lib.check(lib.sv_set_basis(ref.handle, 0))
+    _lib.check(lib.sv_run(ref.handle, sv._opptr(ops), len(circ), None, 0, sv.SV_RUN_TILED))
+    torch.cuda.synchronize()
+    st = sv.State(n, "c64")
+    nb = ctypes.c_int()
+    variants = [("plain", 0, 0), ("fused_k4_fp32", 4, sv.SV_PREC_FP32),
+                ("fused_k4_bf16x3", 4, sv.SV_PREC_SPLIT_BF16), ("fused_k5_fp32", 5, sv.SV_PREC_FP32),
+                ("fused_k5_bf16x3", 5, sv.SV_PREC_SPLIT_BF16)]
+    res = {}
+    for label, k, prec in variants:
+        def step():
+            _lib.check(lib.sv_set_basis(st.handle, 0))
+            if k == 0:
+                _lib.check(lib.sv_run(st.handle, sv._opptr(ops), len(circ), None, 0, sv.SV_RUN_TILED))
+            else:
+                _lib.check(lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ), None, 0, k, prec,
+                                            ctypes.byref(nb)))
+        for _ in range(warmup):
+            step()
+        _lib.check(lib.sv_timing(st.handle, 1))
+        dt = timed(step, steps, torch)
+        per = read_stats(lib, st.handle)
+        _lib.check(lib.sv_timing(st.handle, 0))
+        fid, mx = compare_states(st.amps, ref.amps, torch)
+        kern = "fused_block" if k else "tile_pass"
+        kc, kms, kby, kfl = per.get(kern, (1, 0.0, 0.0, 0.0))
+        res[label] = {"updates_per_s": circ.updates() * steps / dt, "ms_per_step": dt / steps * 1e3,
+                      "blocks": nb.value if k else None, "pass_launches": kc // steps,
+                      "pass_avg_ms": round(kms / kc, 3) if kc else None,
+                      "pass_GBps": round(kby / (kms * 1e-3) / 1e9, 1) if kms > 0 else None,
+                      "infidelity_vs_c128": 1.0 - fid, "max_abs_err_vs_c128": mx}
+    del st, ref
+    fused = {k: v for k, v in res.items() if k != "plain"}
+    best = max(fused, key=lambda k: fused[k]["updates_per_s"])
+    return {"workload": f"{n}-qubit random circuit, depth 40 (1q layer + {n // 2} CZ), complex64, seed {seed}",
+            "gates": len(circ), "updates_per_step": circ.updates(), "variants": res, "best_fused": best,
+            "speedup_best_fused_vs_plain": res[best]["updates_per_s"] / res["plain"]["updates_per_s"]}
 
 
 def timed(fn, steps, torch):
@@ -162,32 +290,11 @@ def other_workload(args):
     out = {"metric": "gate-amplitude updates/s", "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "data": "synthetic", "vs_baseline": None}
     if args.workload == "fusion":
-        circ = C.config2(n=30, seed=args.seed, depth=40)
-        st = sv.State(30, "c64")
-        ops = sv.ops_from_gates(circ.gates)
-        res = {}
-        nb = ctypes.c_int()
-        for label, fn in [("plain", lambda: lib.sv_run(st.handle, sv._opptr(ops), len(circ), None, 0,
-                                                       sv.SV_RUN_TILED)),
-                          ("fused_k4_fp32", lambda: lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ), None,
-                                                                     0, 4, sv.SV_PREC_FP32, ctypes.byref(nb))),
-                          ("fused_k5_fp32", lambda: lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ), None,
-                                                                     0, 5, sv.SV_PREC_FP32, ctypes.byref(nb))),
-                          ("fused_k5_bf16x3", lambda: lib.sv_run_fused(st.handle, sv._opptr(ops), len(circ),
-                                                                       None, 0, 5, sv.SV_PREC_SPLIT_BF16,
-                                                                       ctypes.byref(nb)))]:
-            def step():
-                _lib.check(lib.sv_set_basis(st.handle, 0))
-                _lib.check(fn())
-            for _ in range(args.warmup):
-                step()
-            dt = timed(step, args.steps, torch)
-            res[label] = {"updates_per_s": circ.updates() * args.steps / dt,
-                          "ms_per_step": dt / args.steps * 1e3,
-                          "blocks": nb.value if label != "plain" else None}
-        out.update({"value": res["fused_k5_bf16x3"]["updates_per_s"], "dtype": "f32",
-                    "config": {"workload": "30-qubit random circuit, depth 40 (1q layer + 15 CZ), complex64"},
-                    "variants": res})
+        f = bench_fusion(30, args.seed, args.steps, args.warmup, torch)
+        best = f["variants"][f["best_fused"]]
+        out.update({"value": best["updates_per_s"], "dtype": "f32",
+                    "config": {"workload": f["workload"], "variant": f["best_fused"]},
+                    "ms_per_step": best["ms_per_step"], "fusion": f})
     elif args.workload == "batch":
         circs = [c.bound() for c in C.config3(seed=args.seed)]
         b = sv.Batch(circs, "c64", z_mask=1)
@@ -306,9 +413,8 @@ def main():
         per = read_stats(lib, r["state"].handle)
         _lib.check(lib.sv_timing(r["state"].handle, 0))
         r["kernels"] = per
-        for name, (cnt, ms, by) in per.items():
-            key = f"{name}@{r['n']}q_{r['dtype']}"
-            stats[key] = (cnt, ms, by)
+        for name, v in per.items():
+            stats[f"{name}@{r['n']}q_{r['dtype']}"] = v
 
     elapsed = t1 - t0
     total_updates = sum(r["updates"] for r in regs) * args.steps
@@ -316,13 +422,7 @@ def main():
     value = total_updates / elapsed
 
     dom_key = max(stats, key=lambda k: stats[k][1])
-    cnt, ms, by = stats[dom_key]
-    avg_ms = ms / cnt
-    achieved = (by / cnt) / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom_key, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches": cnt, "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": by / cnt}
+    roofline = roofline_of(dom_key, *stats[dom_key])
 
     breakdown = {}
     for r in regs:
@@ -332,14 +432,20 @@ def main():
             "updates_per_step": r["updates"],
             "kernel_ms_per_step": round(kern_ms / args.steps, 3),
             "kernels": {k: {"launches": v[0] // args.steps, "ms_per_step": round(v[1] / args.steps, 3),
-                            "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                            "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None,
+                            "TFLOPs": round(v[3] / (v[1] * 1e-3) / 1e12, 2) if v[1] > 0 else None}
                         for k, v in r["kernels"].items()},
             "norm": r["norm"], "z0": r["z0"],
         }
 
     fused = None
     if not args.no_fused:
-        fused = bench_fused(args, regs, lib, sv, _lib, torch)
+        same = bench_fused(args, regs, lib, sv, _lib, torch)
+        for r in regs:  # free the registers before the fusion workload's states
+            r["state"] = None
+            r["probs"] = None
+        torch.cuda.empty_cache()
+        fused = {"fusion_workload": bench_fusion(30, args.seed, args.steps, 1, torch), "same_workload": same}
 
     cpu = None
     if not args.no_cpu:

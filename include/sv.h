@@ -235,13 +235,17 @@ int sv_batch_free(sv_batch_handle b);
  * that ran since the record was cleared: launches, summed event time and the
  * summed algorithmic HBM bytes of those launches (every amplitude a launch
  * must read and write once: 2 * bytes-per-amplitude * amplitudes touched for
- * a gate or tile pass).  *n_out receives the number of kinds; SV_EINVAL if it
- * exceeds cap.  Reading clears the record. */
+ * a gate or tile pass) and their algorithmic floating-point operations (per
+ * updated amplitude: 14 for a general 2x2 complex matvec, 6 for a real 2x2
+ * or a diagonal, 3 on average for a phase gate, 0 for a swap, 30 for a 4x4,
+ * 8 * 2^k for a k-qubit dense block).  *n_out receives the number of kinds;
+ * SV_EINVAL if it exceeds cap.  Reading clears the record. */
 typedef struct sv_kernel_stat {
     char name[24];
     int64_t launches;
     double total_ms;
-    double bytes;
+    double bytes;  /* algorithmic HBM bytes of all launches */
+    double flops;  /* algorithmic floating-point operations of all launches */
 } sv_kernel_stat;
 int sv_timing(sv_handle h, int enable);
 int sv_timing_read(sv_handle h, sv_kernel_stat *out, int cap, int *n_out);

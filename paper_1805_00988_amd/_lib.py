@@ -38,7 +38,7 @@ class sv_op(ctypes.Structure):
 
 class sv_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
-                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class SVError(RuntimeError):

@@ -169,15 +169,14 @@ __device__ __forceinline__ double probe_gate(const cpx<T> (&v)[1 << W], const cp
 }
 
 template <typename T, int W>
-__global__ __launch_bounds__(256) void k_adjoint_tile(typename AV<T>::type *psi, typename AV<T>::type *lam,
+__global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::type *psi, typename AV<T>::type *lam,
                                                       TileSpec sp, int m, const TileSweep *__restrict__ sweeps,
                                                       int n_sweeps, const TileGate *__restrict__ gates,
                                                       int slot0, int n_slots, double *partials,
                                                       uint64_t n_tiles) {
-    using V = AV<T>;
     constexpr int D = 1 << W;
     extern __shared__ char lds_raw[];
-    const uint32_t tsize = 1u << m, tvec = tsize >> V::bits;
+    const uint32_t tsize = 1u << m;
     cpx<T> *lp = reinterpret_cast<cpx<T> *>(lds_raw);
     cpx<T> *ll = lp + tsize;
     __shared__ double slot_acc[kMaxAdjSlots];
@@ -186,19 +185,8 @@ __global__ __launch_bounds__(256) void k_adjoint_tile(typename AV<T>::type *psi,
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        for (uint32_t l = threadIdx.x; l < tvec; l += blockDim.x) {
-            const uint32_t la = l << V::bits;
-            uint64_t g = base | (la & ((1u << sp.L) - 1u));
-            const uint32_t hi = la >> sp.L;
-            for (int i = 0; i < sp.K; ++i)
-                if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
-            const typename V::type a = psi[g >> V::bits], b = lam[g >> V::bits];
-#pragma unroll
-            for (int k = 0; k < V::amps; ++k) {
-                lp[lds_phys<T>(la + k)] = V::get(a, k);
-                ll[lds_phys<T>(la + k)] = V::get(b, k);
-            }
-        }
+        tile_load<T, kAdjThreads, 4>(psi, lp, sp, base, tsize);
+        tile_load<T, kAdjThreads, 4>(lam, ll, sp, base, tsize);
         __syncthreads();
         int goff = 0;
         for (int si = 0; si < n_sweeps; ++si) {
@@ -261,21 +249,8 @@ __global__ __launch_bounds__(256) void k_adjoint_tile(typename AV<T>::type *psi,
             goff += ng;
             __syncthreads();
         }
-        for (uint32_t l = threadIdx.x; l < tvec; l += blockDim.x) {
-            const uint32_t la = l << V::bits;
-            uint64_t g = base | (la & ((1u << sp.L) - 1u));
-            const uint32_t hi = la >> sp.L;
-            for (int i = 0; i < sp.K; ++i)
-                if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
-            typename V::type a, b;
-#pragma unroll
-            for (int k = 0; k < V::amps; ++k) {
-                V::put(a, k, lp[lds_phys<T>(la + k)]);
-                V::put(b, k, ll[lds_phys<T>(la + k)]);
-            }
-            psi[g >> V::bits] = a;
-            lam[g >> V::bits] = b;
-        }
+        tile_store<T, kAdjThreads, 4>(psi, lp, sp, base, tsize);
+        tile_store<T, kAdjThreads, 4>(lam, ll, sp, base, tsize);
         __syncthreads();
     }
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x)

@@ -37,68 +37,13 @@ __device__ __forceinline__ uint32_t deposit(uint32_t x, const int *pos, int nbit
     return r;
 }
 
-// Tile staging shared with the gate tile pass (same index mapping and the
-// same swizzled LDS layout; lds_phys is linear over XOR, so the address of a
-// deposit of disjoint index parts is the XOR of the parts' addresses).
+// Tile index mapping and swizzled LDS layout are those of the gate tile
+// pass (lds_phys is linear over XOR, so the address of a deposit of
+// disjoint index parts is the XOR of the parts' addresses).
 __device__ __forceinline__ uint64_t tile_base(const TileSpec &sp, uint64_t tile) {
     uint64_t base = tile << sp.L;
     for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
     return base;
-}
-
-__device__ __forceinline__ uint64_t tile_addr(const TileSpec &sp, uint64_t base, uint32_t l) {
-    uint64_t g = base | (l & ((1u << sp.L) - 1u));
-    const uint32_t hi = l >> sp.L;
-    for (int i = 0; i < sp.K; ++i)
-        if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
-    return g;
-}
-
-template <typename T>
-struct V16;
-template <>
-struct V16<float> {
-    using type = float4;
-    static constexpr int bits = 1;
-};
-template <>
-struct V16<double> {
-    using type = double2;
-    static constexpr int bits = 0;
-};
-
-template <typename T>
-__device__ __forceinline__ void stage_in(const typename V16<T>::type *v, cpx<T> *lds,
-                                         const TileSpec &sp, uint64_t base, uint32_t tsize) {
-    constexpr int vb = V16<T>::bits;
-    for (uint32_t l = threadIdx.x; l < (tsize >> vb); l += blockDim.x) {
-        const uint32_t la = l << vb;
-        const typename V16<T>::type w = v[tile_addr(sp, base, la) >> vb];
-        if constexpr (vb == 1) {
-            lds[lds_phys<T>(la)] = cpx<T>{w.x, w.y};
-            lds[lds_phys<T>(la + 1)] = cpx<T>{w.z, w.w};
-        } else {
-            lds[lds_phys<T>(la)] = cpx<T>{w.x, w.y};
-        }
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void stage_out(typename V16<T>::type *v, const cpx<T> *lds,
-                                          const TileSpec &sp, uint64_t base, uint32_t tsize) {
-    constexpr int vb = V16<T>::bits;
-    for (uint32_t l = threadIdx.x; l < (tsize >> vb); l += blockDim.x) {
-        const uint32_t la = l << vb;
-        typename V16<T>::type w;
-        if constexpr (vb == 1) {
-            const cpx<T> a = lds[lds_phys<T>(la)], b = lds[lds_phys<T>(la + 1)];
-            w = float4{a.re, a.im, b.re, b.im};
-        } else {
-            const cpx<T> a = lds[lds_phys<T>(la)];
-            w = double2{a.re, a.im};
-        }
-        v[tile_addr(sp, base, la) >> vb] = w;
-    }
 }
 
 // ------------------------------------------------- native (vector ALU)
@@ -107,7 +52,7 @@ __device__ __forceinline__ void stage_out(typename V16<T>::type *v, const cpx<T>
 // scalar cache), written back to the group's own LDS slots.  The blocks of a
 // pass are applied one after another to the staged tile.
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_dense_native(typename V16<T>::type *v, TileSpec sp, int m,
+__global__ __launch_bounds__(256) void k_dense_native(typename Amp16<T>::type *v, TileSpec sp, int m,
                                                       const DenseBlock *__restrict__ blocks, int n_blocks,
                                                       const char *__restrict__ base_ptr,
                                                       uint64_t n_tiles) {
@@ -118,7 +63,7 @@ __global__ __launch_bounds__(256) void k_dense_native(typename V16<T>::type *v, 
     const uint32_t n_groups = tsize >> K;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
-        stage_in<T>(v, lds, sp, base, tsize);
+        tile_load<T, 256, 8>(v, lds, sp, base, tsize);
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
@@ -141,7 +86,7 @@ __global__ __launch_bounds__(256) void k_dense_native(typename V16<T>::type *v, 
             }
             __syncthreads();
         }
-        stage_out<T>(v, lds, sp, base, tsize);
+        tile_store<T, 256, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
 }
@@ -212,7 +157,7 @@ __global__ __launch_bounds__(Bf16Cfg<K>::threads) void k_dense_bf16(float4 *v, T
     const int r = lane % ROWS, kk = lane / ROWS;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
-        stage_in<float>(v, lds, sp, base, tsize);
+        tile_load<float, Bf16Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
@@ -266,7 +211,7 @@ __global__ __launch_bounds__(Bf16Cfg<K>::threads) void k_dense_bf16(float4 *v, T
             }
             __syncthreads();
         }
-        stage_out<float>(v, lds, sp, base, tsize);
+        tile_store<float, Bf16Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
 }
@@ -305,7 +250,7 @@ __global__ __launch_bounds__(F32Cfg<K>::threads) void k_dense_f32(float4 *v, Til
     const int r = lane % ROWS, kk = lane / ROWS;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
-        stage_in<float>(v, lds, sp, base, tsize);
+        tile_load<float, F32Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
@@ -347,7 +292,7 @@ __global__ __launch_bounds__(F32Cfg<K>::threads) void k_dense_f32(float4 *v, Til
             }
             __syncthreads();
         }
-        stage_out<float>(v, lds, sp, base, tsize);
+        tile_store<float, F32Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
 }
@@ -375,7 +320,7 @@ __global__ __launch_bounds__(256) void k_dense_f64(double2 *v, TileSpec sp, int 
     const int r = lane & 15, kk = lane >> 4;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
-        stage_in<double>(v, lds, sp, base, tsize);
+        tile_load<double, 256, 8>(v, lds, sp, base, tsize);
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
@@ -420,7 +365,7 @@ __global__ __launch_bounds__(256) void k_dense_f64(double2 *v, TileSpec sp, int 
             }
             __syncthreads();
         }
-        stage_out<double>(v, lds, sp, base, tsize);
+        tile_store<double, 256, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
 }

@@ -376,28 +376,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v,
     using V = Vec<T>;
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
-    const uint32_t tvec = (1u << m) >> V::bits;
+    const uint32_t tsize = 1u << m;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        // element l covers local amplitudes l*VA .. l*VA+VA-1 (L >= vector bits)
-        for (uint32_t l = threadIdx.x; l < tvec; l += kTileThreads) {
-            const uint32_t la = l << V::bits;
-            const typename V::type w = v[tile_global(sp, base, la) >> V::bits];
-#pragma unroll
-            for (int k = 0; k < V::amps; ++k) lds[lds_phys<T>(la + k)] = V::get(w, k);
-        }
+        tile_load<T, kTileThreads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
         tile_run_sweeps<T, W>(lds, m, base, sweeps, n_sweeps, gates);
-        for (uint32_t l = threadIdx.x; l < tvec; l += kTileThreads) {
-            const uint32_t la = l << V::bits;
-            typename V::type w;
-#pragma unroll
-            for (int k = 0; k < V::amps; ++k) V::put(w, k, lds[lds_phys<T>(la + k)]);
-            v[tile_global(sp, base, la) >> V::bits] = w;
-        }
+        tile_store<T, kTileThreads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
+    (void)sizeof(V);
 }
 
 template <typename T, int W>

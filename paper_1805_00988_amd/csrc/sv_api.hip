@@ -31,7 +31,7 @@ struct sv_state {
     // per-launch timing (sv_timing): event pairs around each kernel launch
     struct Rec {
         int kid;
-        double bytes;
+        double bytes, flops;
         hipEvent_t a, b;
     };
     double *d_scratch = nullptr;      // adjoint partial sums
@@ -80,13 +80,15 @@ static hipEvent_t take_event(sv_state *h) {
 }
 
 // Brackets one kernel launch with events on the handle's stream when timing
-// is on; 'bytes' is the algorithmic HBM traffic of the launch.
+// is on; 'bytes' is the algorithmic HBM traffic of the launch and 'flops'
+// its algorithmic floating-point operations.
 struct Timed {
     sv_state *h;
     int kid;
-    double bytes;
+    double bytes, flops;
     hipEvent_t a = nullptr;
-    Timed(sv_state *h_, int kid_, double bytes_) : h(h_), kid(kid_), bytes(bytes_) {
+    Timed(sv_state *h_, int kid_, double bytes_, double flops_ = 0.0)
+        : h(h_), kid(kid_), bytes(bytes_), flops(flops_) {
         if (h->timing && (a = take_event(h)) != nullptr) (void)hipEventRecord(a, h->stream);
     }
     ~Timed() {
@@ -94,7 +96,7 @@ struct Timed {
         hipEvent_t b = take_event(h);
         if (!b) return;
         (void)hipEventRecord(b, h->stream);
-        h->recs.push_back({kid, bytes, a, b});
+        h->recs.push_back({kid, bytes, flops, a, b});
     }
 };
 
@@ -226,6 +228,8 @@ static int vbits_of(int dtype) { return dtype == SV_C64 ? 1 : 0; }
 // complex64 state, whose pair partner is inside a 16-byte vector).
 static int tile_single(sv_state *h, const Gate &g);
 
+static double gate_flops_per_amp(const Gate &g);
+
 static int apply_one(sv_state *h, const Gate &g) {
     if (g.k == 1) {
         const double *U = g.U;
@@ -233,18 +237,21 @@ static int apply_one(sv_state *h, const Gate &g) {
             if (is_one(U) && is_one(U + 6)) return SV_OK; // identity
             if (is_one(U)) {
                 const uint64_t mask = g.ctrl | (1ull << g.t[0]);
-                Timed tm(h, K_SCALE, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(mask)));
+                Timed tm(h, K_SCALE, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(mask)),
+                         6.0 * (double)(1ull << h->n) / (double)(1ull << __builtin_popcountll(mask)));
                 SV_HIP(launch_scale(h->amps, h->n, h->dtype, mask, U + 6, h->stream));
                 return SV_OK;
             }
         }
-        Timed tm(h, K_GATE1, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(g.ctrl)));
+        Timed tm(h, K_GATE1, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(g.ctrl)),
+                 gate_flops_per_amp(g) * (double)(1ull << h->n));
         SV_HIP(launch_gate1(h->amps, h->n, h->dtype, g.t[0], g.ctrl, g.U, h->stream));
         return SV_OK;
     }
     const int vb = vbits_of(h->dtype);
     if (g.t[0] >= vb && g.t[1] >= vb) {
-        Timed tm(h, K_GATE2, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(g.ctrl)));
+        Timed tm(h, K_GATE2, 2.0 * state_bytes(h) / (double)(1ull << __builtin_popcountll(g.ctrl)),
+                 gate_flops_per_amp(g) * (double)(1ull << h->n));
         SV_HIP(launch_gate2(h->amps, h->n, h->dtype, g.t[0], g.t[1], g.ctrl, g.U, h->stream));
         return SV_OK;
     }
@@ -289,6 +296,7 @@ static int local_bit(const TileSpec &sp, int q) {
 struct PassCode {
     TileSpec sp{};
     int m = 0;
+    double flops_per_amp = 0.0; // algorithmic flops of the pass per state amplitude
     std::vector<TileSweep> sweeps;
     std::vector<TileGate> gates;
     size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + gates.size() * sizeof(TileGate); }
@@ -319,6 +327,22 @@ static void put_matrix(TileGate &r, const double *U, int n, bool f32) {
     }
     float *f = reinterpret_cast<float *>(r.m);
     for (int i = 0; i < 2 * n; ++i) f[i] = (float)U[i];
+}
+
+// Algorithmic floating-point operations per updated amplitude of a gate:
+// general 2x2 complex matvec 14 (two complex products and a sum per
+// output), real 2x2 6, diagonal 6 (3 on average for a phase gate, which
+// changes half of the amplitudes), swap 0, general 4x4 30.  A gate with c
+// controls updates 2^-c of the state.
+static double gate_flops_per_amp(const Gate &g) {
+    double f;
+    if (is_diag1(g)) f = is_one(g.U) ? 3.0 : 6.0;
+    else if (g.k == 1) {
+        bool real = true;
+        for (int i = 0; i < 4; ++i) real = real && g.U[2 * i + 1] == 0.0;
+        f = is_x(g) ? 0.0 : (real ? 6.0 : 14.0);
+    } else f = 30.0;
+    return f / (double)(1ull << __builtin_popcountll(g.ctrl));
 }
 
 static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qset, const Gate &g,
@@ -417,9 +441,12 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
             if (const Probe *pr = probe_of(i)) {
                 pc.gates.push_back(encode_probe(sp, qset, *gs[i], *pr, f32));
                 ++sw.n_gates;
+                // probe: Im<lam|M|psi> over the gate's pairs, 8 flops per amplitude
+                pc.flops_per_amp += 8.0 / (double)(1ull << __builtin_popcountll(gs[i]->ctrl));
             }
             pc.gates.push_back(encode_sweep_gate(sp, qset, *gs[i], f32));
             ++sw.n_gates;
+            pc.flops_per_amp += (probes ? 2.0 : 1.0) * gate_flops_per_amp(*gs[i]);
         }
         for (int j = 0; j < kSweepW; ++j) sw.qpos[j] = j < W ? qset[j] : 0;
         pc.sweeps.push_back(sw);
@@ -459,7 +486,7 @@ static int launch_pass(sv_state *h, const PassCode &pc, size_t off) {
     const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + off);
     const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + off +
                                                             align256(pc.sweeps.size() * sizeof(TileSweep)));
-    Timed tm(h, K_TILE, 2.0 * state_bytes(h));
+    Timed tm(h, K_TILE, 2.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
     SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, h->stream));
     return SV_OK;
 }
@@ -787,6 +814,7 @@ static bool mfma_ok(const sv_state *h, int k, int prec) {
 struct FusedPass {
     TileSpec sp{};
     int m = 0;
+    double flops_per_amp = 0.0; // 8 * 2^k per block of k qubits (complex matvec as real flops)
     int k = 0;
     int engine = SV_PREC_NATIVE;
     std::vector<DenseBlock> blocks;
@@ -873,6 +901,7 @@ static FusedPass build_fused_pass(const sv_state *h, const std::vector<Block> &b
             if (!((used >> b) & 1u)) db.bp.gpos[db.bp.ng++] = b;
         fp.blocks.push_back(db);
         fp.mats.push_back(B.k == fp.k ? B.M : pad_matrix(B.M, B.k, fp.k));
+        fp.flops_per_amp += 8.0 * (double)(1 << B.k);
     }
     return fp;
 }
@@ -964,7 +993,7 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
 }
 
 static int launch_fused(sv_state *h, const FusedPass &fp, size_t off) {
-    Timed tm(h, K_FUSED, 2.0 * state_bytes(h));
+    Timed tm(h, K_FUSED, 2.0 * state_bytes(h), fp.flops_per_amp * (double)(1ull << h->n));
     SV_HIP(launch_dense_pass(h->amps, h->n, h->dtype, fp.sp, fp.k,
                              reinterpret_cast<const DenseBlock *>(h->d_arena + off), (int)fp.blocks.size(),
                              h->d_arena, fp.engine, h->stream));
@@ -1413,6 +1442,7 @@ int sv_timing_read(sv_handle h, sv_kernel_stat *out, int cap, int *n_out) {
         acc[r.kid].launches += 1;
         acc[r.kid].total_ms += ms;
         acc[r.kid].bytes += r.bytes;
+        acc[r.kid].flops += r.flops;
     }
     int n = 0;
     for (int k = 0; k < K_COUNT; ++k) {
@@ -1626,7 +1656,7 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, con
         const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + offs[pi]);
         const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + offs[pi] +
                                                                 align256(pc.sweeps.size() * sizeof(TileSweep)));
-        Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h));
+        Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
         hipError_t e = launch_adjoint_tile(h->amps, lam->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt,
                                            slot0[pi], nslot[pi], partials + loss_n, B, h->stream);
         if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_tile"));

@@ -24,6 +24,100 @@ __device__ __forceinline__ uint32_t lds_phys(uint32_t l) {
     return lds_swizzle(l, lds_swizzle_bits(2 * sizeof(T)));
 }
 
+// ------------------------------------------------------------ tile staging
+// 16-byte vectors of amplitudes: two complex64 or one complex128.
+template <typename T>
+struct Amp16;
+template <>
+struct Amp16<float> {
+    using type = float4;
+    static constexpr int bits = 1;
+};
+template <>
+struct Amp16<double> {
+    using type = double2;
+    static constexpr int bits = 0;
+};
+
+// Offset of local amplitude l from the tile's base index: the low L bits in
+// place, bit L + i at global position high[i].  The map is linear over the
+// OR of parts with disjoint bits.
+__device__ __forceinline__ uint64_t tile_offset(const TileSpec &sp, uint32_t l) {
+    uint64_t g = l & ((1u << sp.L) - 1u);
+    const uint32_t hi = l >> sp.L;
+#pragma unroll
+    for (int i = 0; i < kMaxTileHigh; ++i) {
+        if (i >= sp.K) break;
+        if ((hi >> i) & 1u) g |= 1ull << sp.high[i];
+    }
+    return g;
+}
+
+// Copy a tile of tsize amplitudes between the state and the swizzled LDS
+// tile with NTH threads.  Thread t moves the 16-byte vectors at local index
+// t*VA + r*STRIDE (VA amplitudes per vector, STRIDE = NTH*VA) for rounds r;
+// U rounds are issued before any of their results is used, so a lane keeps
+// U memory accesses in flight.  Both addresses split into a per-thread part
+// and a wave-uniform per-round part (disjoint bits, combined by OR / XOR).
+template <typename T, int NTH, int U>
+__device__ __forceinline__ void tile_load(const typename Amp16<T>::type *__restrict__ v, cpx<T> *lds,
+                                          const TileSpec &sp, uint64_t base, uint32_t tsize) {
+    constexpr int vb = Amp16<T>::bits;
+    constexpr uint32_t STRIDE = (uint32_t)NTH << vb;
+    const uint32_t lt = threadIdx.x << vb;
+    const uint64_t gt = base | tile_offset(sp, lt);
+    const uint32_t pt = lds_phys<T>(lt);
+    for (uint32_t r0 = 0; r0 < tsize; r0 += U * STRIDE) {
+        typename Amp16<T>::type w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t ru = r0 + u * STRIDE;
+            if (ru + lt < tsize) w[u] = v[(gt | tile_offset(sp, ru)) >> vb];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t ru = r0 + u * STRIDE;
+            if (ru + lt < tsize) {
+                const uint32_t p = lds_phys<T>(ru) ^ pt;
+                lds[p] = cpx<T>{w[u].x, w[u].y};
+                if constexpr (vb == 1) lds[p ^ 1u] = cpx<T>{w[u].z, w[u].w};
+            }
+        }
+    }
+}
+
+template <typename T, int NTH, int U>
+__device__ __forceinline__ void tile_store(typename Amp16<T>::type *__restrict__ v, const cpx<T> *lds,
+                                           const TileSpec &sp, uint64_t base, uint32_t tsize) {
+    constexpr int vb = Amp16<T>::bits;
+    constexpr uint32_t STRIDE = (uint32_t)NTH << vb;
+    const uint32_t lt = threadIdx.x << vb;
+    const uint64_t gt = base | tile_offset(sp, lt);
+    const uint32_t pt = lds_phys<T>(lt);
+    for (uint32_t r0 = 0; r0 < tsize; r0 += U * STRIDE) {
+        typename Amp16<T>::type w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t ru = r0 + u * STRIDE;
+            if (ru + lt < tsize) {
+                const uint32_t p = lds_phys<T>(ru) ^ pt;
+                const cpx<T> a = lds[p];
+                if constexpr (vb == 1) {
+                    const cpx<T> b = lds[p ^ 1u];
+                    w[u] = typename Amp16<T>::type{a.re, a.im, b.re, b.im};
+                } else {
+                    w[u] = typename Amp16<T>::type{a.re, a.im};
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t ru = r0 + u * STRIDE;
+            if (ru + lt < tsize) v[(gt | tile_offset(sp, ru)) >> vb] = w[u];
+        }
+    }
+}
+
 // Matrix entry i of a record, stored in the state's own precision.
 template <typename T>
 __device__ __forceinline__ cpx<T> gmat(const TileGate &G, int i) {
@@ -35,6 +129,58 @@ __device__ __forceinline__ T gre(const TileGate &G, int i) {
     return reinterpret_cast<const T *>(G.m)[2 * i];
 }
 
+// x *= d with each component's own term taken last (see sweep_1q).
+template <typename T>
+__device__ __forceinline__ void cmul_inplace(cpx<T> &x, cpx<T> d) {
+    const T a = -d.im * x.im, b = d.im * x.re;
+    x.re = fma(d.re, x.re, a);
+    x.im = fma(d.re, x.im, b);
+}
+
+// Exchange two amplitudes held in registers without renaming registers
+// (a renamed set cannot share registers with the paths that leave the
+// group unchanged, and every gate then pays a copy of the whole group).
+__device__ __forceinline__ void swap_words(uint32_t &a, uint32_t &b) {
+    asm volatile("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap_f(float &a, float &b) {
+    uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
+    swap_words(x, y);
+    a = __builtin_bit_cast(float, x);
+    b = __builtin_bit_cast(float, y);
+}
+__device__ __forceinline__ void swap_f(double &a, double &b) {
+    uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+    uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32), yl = (uint32_t)y, yh = (uint32_t)(y >> 32);
+    swap_words(xl, yl);
+    swap_words(xh, yh);
+    a = __builtin_bit_cast(double, ((uint64_t)xh << 32) | xl);
+    b = __builtin_bit_cast(double, ((uint64_t)yh << 32) | yl);
+}
+template <typename T>
+__device__ __forceinline__ void swap_regs(cpx<T> &a, cpx<T> &b) {
+    swap_f(a.re, b.re);
+    swap_f(a.im, b.im);
+}
+// Conditional exchange: a ^= d, b ^= d with d = (a ^ b) masked by the condition.
+template <typename U>
+__device__ __forceinline__ void xswap(U &a, U &b, U mask) {
+    const U d = (a ^ b) & mask;
+    a ^= d;
+    b ^= d;
+}
+template <typename T>
+__device__ __forceinline__ void swap_if(cpx<T> &a, cpx<T> &b, bool cond) {
+    using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+    const U mask = cond ? ~(U)0 : (U)0;
+    U ar = __builtin_bit_cast(U, a.re), ai = __builtin_bit_cast(U, a.im);
+    U br = __builtin_bit_cast(U, b.re), bi = __builtin_bit_cast(U, b.im);
+    xswap(ar, br, mask);
+    xswap(ai, bi, mask);
+    a = cpx<T>{__builtin_bit_cast(T, ar), __builtin_bit_cast(T, ai)};
+    b = cpx<T>{__builtin_bit_cast(T, br), __builtin_bit_cast(T, bi)};
+}
+
 // The local index of amplitude j of a group is gb | F[j] (gb: the group's
 // bits, F[j]: j's bits deposited at the sweep's register positions, uniform).
 // Control tests are compiled out for gates without controls inside the tile.
@@ -44,6 +190,9 @@ template <typename T, int W, int P, bool CHECK>
 __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&li)[1 << W],
                                          const TileGate &G, int kind, uint32_t cin) {
     constexpr int D = 1 << W;
+    // Every output first collects the terms that do not read its own input
+    // component, then takes that component in one final FMA: the input dies
+    // at its last use and the result can stay in the same register.
     if (kind == SK_GEN) {
         const cpx<T> g0 = gmat<T>(G, 0), g1 = gmat<T>(G, 1), g2 = gmat<T>(G, 2), g3 = gmat<T>(G, 3);
 #pragma unroll
@@ -52,8 +201,12 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&l
             if (CHECK && (li[j] & cin) != cin) continue;
             const int c = j | (1 << P);
             const cpx<T> x0 = v[j], x1 = v[c];
-            v[j] = cfma(g0, x0, cmul(g1, x1));
-            v[c] = cfma(g2, x0, cmul(g3, x1));
+            const T a_re = fma(g1.re, x1.re, fma(-g1.im, x1.im, -g0.im * x0.im));
+            const T a_im = fma(g1.re, x1.im, fma(g1.im, x1.re, g0.im * x0.re));
+            const T b_re = fma(g2.re, x0.re, fma(-g2.im, x0.im, -g3.im * x1.im));
+            const T b_im = fma(g2.re, x0.im, fma(g2.im, x0.re, g3.im * x1.re));
+            v[j] = cpx<T>{fma(g0.re, x0.re, a_re), fma(g0.re, x0.im, a_im)};
+            v[c] = cpx<T>{fma(g3.re, x1.re, b_re), fma(g3.re, x1.im, b_im)};
         }
     } else if (kind == SK_REAL) {
         const T r0 = gre<T>(G, 0), r1 = gre<T>(G, 1), r2 = gre<T>(G, 2), r3 = gre<T>(G, 3);
@@ -63,18 +216,17 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&l
             if (CHECK && (li[j] & cin) != cin) continue;
             const int c = j | (1 << P);
             const cpx<T> x0 = v[j], x1 = v[c];
-            v[j] = cpx<T>{fma(r0, x0.re, r1 * x1.re), fma(r0, x0.im, r1 * x1.im)};
-            v[c] = cpx<T>{fma(r2, x0.re, r3 * x1.re), fma(r2, x0.im, r3 * x1.im)};
+            const T a_re = r1 * x1.re, a_im = r1 * x1.im, b_re = r2 * x0.re, b_im = r2 * x0.im;
+            v[j] = cpx<T>{fma(r0, x0.re, a_re), fma(r0, x0.im, a_im)};
+            v[c] = cpx<T>{fma(r3, x1.re, b_re), fma(r3, x1.im, b_im)};
         }
-    } else { // SK_SWAP
+    } else { // SK_SWAP: exchanged in place, so no register is renamed
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (j & (1 << P)) continue;
-            if (CHECK && (li[j] & cin) != cin) continue;
             const int c = j | (1 << P);
-            const cpx<T> x0 = v[j];
-            v[j] = v[c];
-            v[c] = x0;
+            if (CHECK) swap_if(v[j], v[c], (li[j] & cin) == cin);
+            else swap_regs(v[j], v[c]);
         }
     }
 }
@@ -88,15 +240,23 @@ __device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], const uint32_t (&l
         if (j & ((1 << P) | (1 << Q))) continue;
         if (CHECK && (li[j] & cin) != cin) continue;
         const int idx[4] = {j, j | (1 << P), j | (1 << Q), j | (1 << P) | (1 << Q)};
-        cpx<T> x[4];
+        cpx<T> x[4], a[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = v[idx[q]];
+        // partial sums without each output's own component (see sweep_1q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            cpx<T> acc = cmul(gmat<T>(G, 4 * r), x[0]);
+            const cpx<T> d = gmat<T>(G, 5 * r);
+            cpx<T> acc{-d.im * x[r].im, d.im * x[r].re};
 #pragma unroll
-            for (int c = 1; c < 4; ++c) acc = cfma(gmat<T>(G, 4 * r + c), x[c], acc);
-            v[idx[r]] = acc;
+            for (int c = 0; c < 4; ++c)
+                if (c != r) acc = cfma(gmat<T>(G, 4 * r + c), x[c], acc);
+            a[r] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const T dr = gre<T>(G, 5 * r);
+            v[idx[r]] = cpx<T>{fma(dr, x[r].re, a[r].re), fma(dr, x[r].im, a[r].im)};
         }
     }
 }
@@ -113,7 +273,7 @@ __device__ __forceinline__ void sweep_diag(cpx<T> (&v)[1 << W], const uint32_t (
         for (int j = 0; j < D; ++j) {
             const uint32_t l = li[j];
             if (CHECK && (l & cin) != cin) continue;
-            if (l & bm) v[j] = cmul(d1, v[j]);
+            if (l & bm) cmul_inplace(v[j], d1);
         }
     } else {
 #pragma unroll
@@ -121,8 +281,7 @@ __device__ __forceinline__ void sweep_diag(cpx<T> (&v)[1 << W], const uint32_t (
             const uint32_t l = li[j];
             if (CHECK && (l & cin) != cin) continue;
             const bool up = (l & bm) != 0; // component-wise select keeps d0, d1 in registers
-            const cpx<T> d{up ? d1.re : d0.re, up ? d1.im : d0.im};
-            v[j] = cmul(d, v[j]);
+            cmul_inplace(v[j], cpx<T>{up ? d1.re : d0.re, up ? d1.im : d0.im});
         }
     }
 }
