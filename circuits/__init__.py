@@ -254,3 +254,9 @@ def block_product_circuit(n: int, block: int, depth: int, seed: int) -> Tuple[Ci
             for i in range(len(b) // 2):
                 gates.append(Gate("X" if rng.integers(2) else "Z", (sub[2 * i + 1],), (sub[2 * i],)))
     return Circuit(n, gates, 0, None, f"blocks_n{n}_b{block}_d{depth}_s{seed}"), blocks
+
+
+def uniforms(count: int, seed: int) -> np.ndarray:
+    """Seeded uniforms in [0, 1): the random draws of measurement and sampling
+    are inputs to both the oracle and the library."""
+    return _rng(seed).random(count)

@@ -68,6 +68,15 @@ def lib():
                                       _c_cplx_p, _c_f64_p, ctypes.c_int, ctypes.c_int, _c_u64_p,
                                       _c_f64_p, _c_f64_p]
         L.oc_adjoint_grad.restype = ctypes.c_double
+        L.oc_marginals.argtypes = [ctypes.c_int, _c_cplx_p, ctypes.c_uint64, _c_f64_p]
+        L.oc_collapse.argtypes = [ctypes.c_int, _c_cplx_p, ctypes.c_uint64, ctypes.c_uint64]
+        L.oc_collapse.restype = ctypes.c_double
+        L.oc_select.argtypes = [ctypes.c_uint64, _c_f64_p, ctypes.c_double]
+        L.oc_select.restype = ctypes.c_uint64
+        L.oc_sample.argtypes = [ctypes.c_int, _c_cplx_p, ctypes.c_int, _c_f64_p, _c_u64_p]
+        L.oc_measure.argtypes = [ctypes.c_int, _c_cplx_p, ctypes.c_uint64, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_uint64)]
+        L.oc_measure.restype = ctypes.c_double
         L.oc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -173,6 +182,40 @@ def expectation_z(psi: np.ndarray, n: int, masks: Sequence[int], coeffs: Sequenc
     m = np.asarray(masks, np.uint64)
     c = np.asarray(coeffs, np.float64)
     return float(lib().oc_expectation_z(n, psi, len(m), m, c))
+
+
+def marginals(psi: np.ndarray, n: int, mask: int) -> np.ndarray:
+    """Outcome probabilities of the qubits of mask (Sec. 1.3.3)."""
+    out = np.empty(1 << bin(mask).count("1"), np.float64)
+    lib().oc_marginals(n, psi, mask, out)
+    return out
+
+
+def collapse(psi: np.ndarray, n: int, mask: int, value: int) -> float:
+    """Project psi (in place) onto (x & mask) == (value & mask), renormalise; returns p."""
+    return float(lib().oc_collapse(n, psi, mask, value))
+
+
+def select(p: np.ndarray, u: float) -> int:
+    """Inverse-CDF outcome selection over the outcome probabilities p."""
+    p = np.ascontiguousarray(p, np.float64)
+    return int(lib().oc_select(len(p), p, u))
+
+
+def sample(psi: np.ndarray, n: int, uniforms) -> np.ndarray:
+    """Full-register outcomes for the given uniforms in [0, 1); psi unchanged."""
+    u = np.ascontiguousarray(uniforms, np.float64)
+    out = np.empty(len(u), np.uint64)
+    lib().oc_sample(n, psi, len(u), u, out)
+    return out
+
+
+def measure(psi: np.ndarray, n: int, mask: int, u: float) -> Tuple[int, float]:
+    """Measure the qubits of mask with uniform u; psi collapses in place.
+    Returns (outcome bits at the mask positions, probability)."""
+    v = ctypes.c_uint64()
+    p = lib().oc_measure(n, psi, mask, u, ctypes.byref(v))
+    return int(v.value), float(p)
 
 
 def loss(circuit, params: np.ndarray, masks, coeffs) -> float:

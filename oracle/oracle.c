@@ -263,3 +263,78 @@ double oc_adjoint_grad(int n, cplx *psi, cplx *lam, cplx *mu, int n_gates, const
     }
     return loss;
 }
+
+/* ------------------------------------------------------------ measurement */
+/* Outcome index of x for the qubits of mask: bit i = bit of the i-th lowest
+ * qubit in mask. */
+static uint64_t outcome_of(int n, uint64_t x, uint64_t mask) {
+    uint64_t o = 0;
+    int i = 0;
+    for (int b = 0; b < n; ++b) {
+        if (!((mask >> b) & 1ULL)) continue;
+        if ((x >> b) & 1ULL) o |= 1ULL << i;
+        ++i;
+    }
+    return o;
+}
+
+void oc_marginals(int n, const cplx *psi, uint64_t mask, double *out) {
+    const uint64_t dim = 1ULL << n;
+    const int k = __builtin_popcountll(mask);
+    for (uint64_t o = 0; o < (1ULL << k); ++o) out[o] = 0.0;
+    for (uint64_t x = 0; x < dim; ++x) {
+        const double px = creal(psi[x]) * creal(psi[x]) + cimag(psi[x]) * cimag(psi[x]);
+        out[outcome_of(n, x, mask)] += px;
+    }
+}
+
+double oc_collapse(int n, cplx *psi, uint64_t mask, uint64_t value) {
+    const uint64_t dim = 1ULL << n;
+    const uint64_t want = value & mask;
+    double p = 0.0;
+    for (uint64_t x = 0; x < dim; ++x)
+        if ((x & mask) == want) p += creal(psi[x]) * creal(psi[x]) + cimag(psi[x]) * cimag(psi[x]);
+    if (p == 0.0) return 0.0;
+    const double s = 1.0 / sqrt(p);
+    for (uint64_t x = 0; x < dim; ++x) psi[x] = ((x & mask) == want) ? psi[x] * s : 0.0;
+    return p;
+}
+
+uint64_t oc_select(uint64_t m, const double *p, double u) {
+    double total = 0.0;
+    for (uint64_t i = 0; i < m; ++i) total += p[i];
+    const double t = u * total;
+    double c = 0.0;
+    uint64_t last = 0;
+    for (uint64_t i = 0; i < m; ++i) {
+        c += p[i];
+        if (p[i] > 0.0) last = i;
+        if (c > t) return i;
+    }
+    return last;
+}
+
+void oc_sample(int n, const cplx *psi, int n_samples, const double *uniforms, uint64_t *out) {
+    const uint64_t dim = 1ULL << n;
+    double *p = (double *)malloc(dim * sizeof(double));
+    for (uint64_t x = 0; x < dim; ++x) p[x] = creal(psi[x]) * creal(psi[x]) + cimag(psi[x]) * cimag(psi[x]);
+    for (int s = 0; s < n_samples; ++s) out[s] = oc_select(dim, p, uniforms[s]);
+    free(p);
+}
+
+double oc_measure(int n, cplx *psi, uint64_t mask, double u, uint64_t *value) {
+    const int k = __builtin_popcountll(mask);
+    double *marg = (double *)malloc(((size_t)1 << k) * sizeof(double));
+    oc_marginals(n, psi, mask, marg);
+    const uint64_t o = oc_select(1ULL << k, marg, u);
+    free(marg);
+    uint64_t v = 0;
+    int i = 0;
+    for (int b = 0; b < n; ++b) {
+        if (!((mask >> b) & 1ULL)) continue;
+        if ((o >> i) & 1ULL) v |= 1ULL << b;
+        ++i;
+    }
+    *value = v;
+    return oc_collapse(n, psi, mask, v);
+}

@@ -76,6 +76,33 @@ double oc_adjoint_grad(int n, double complex *psi, double complex *lam, double c
                        int n_terms, const uint64_t *masks, const double *coeffs,
                        double *grad);
 
+/* Sec. 1.3.3: measuring the k qubits of 'mask' in the computational basis
+ * (projectors M_o = |o><o| on those qubits) has 2^k outcomes; outcome o
+ * (bit i of o = value of the i-th lowest qubit of mask) has probability
+ * p(o) = <psi|M_o|psi> = sum of |psi_x|^2 over the x whose mask bits spell o.
+ * Writes the 2^k probabilities, summed in index order. */
+void oc_marginals(int n, const double complex *psi, uint64_t mask, double *out);
+
+/* Sec. 1.3.3 post-measurement state M psi / sqrt(p) for the projector M onto
+ * the x with (x & mask) == (value & mask); returns p.  The state is left
+ * unchanged when p == 0. */
+double oc_collapse(int n, double complex *psi, uint64_t mask, uint64_t value);
+
+/* Sec. 2.4 outcome selection from outcome probabilities p[0..m-1], by the
+ * inverse cumulative distribution: with c_i = p_0 + ... + p_i summed in
+ * index order and T = c_{m-1}, the outcome for u in [0, 1) is the smallest i
+ * with c_i > u T (the last i with p_i > 0 if rounding leaves none). */
+uint64_t oc_select(uint64_t m, const double *p, double u);
+
+/* Full-register samples (the state is not changed): outcome s is oc_select
+ * over p_x = |psi_x|^2 with u = uniforms[s]. */
+void oc_sample(int n, const double complex *psi, int n_samples, const double *uniforms, uint64_t *out);
+
+/* Measure the qubits of mask: select an outcome of oc_marginals with u,
+ * collapse onto it, write it (as bits at the mask positions) to *value and
+ * return its probability. */
+double oc_measure(int n, double complex *psi, uint64_t mask, double u, uint64_t *value);
+
 /* Number of OpenMP threads the oracle's loops use. */
 int oc_num_threads(void);
 
