@@ -183,7 +183,38 @@ int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int
 int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
                  int k_max, int prec, int *n_blocks_out);
 
-/* Adjoint-method gradient of L = <psi| H |psi>, H = sum_j coeffs[j] Z^{z_masks[j]},
+/* Sec. 1.3.3: outcome probabilities of measuring the k <= 6 qubits of mask
+ * in the computational basis.  host_out[o] (2^k doubles, host) = sum of
+ * |psi_x|^2 over the x whose mask bits spell o, where bit i of o is the
+ * i-th lowest qubit of mask; FP64, fixed summation order.  The state is not
+ * changed.  SV_EINVAL for an empty mask, bits >= n or more than 6 qubits. */
+int sv_marginals(sv_handle h, uint64_t mask, double *host_out);
+
+/* Sec. 1.3.3 post-measurement state: project onto the x with
+ * (x & mask) == (value & mask) and divide by sqrt(p), p = the FP64
+ * probability of that outcome, written to *host_prob (may be NULL).
+ * SV_EINVAL (state unchanged) if p == 0 or mask has bits >= n. */
+int sv_collapse(sv_handle h, uint64_t mask, uint64_t value, double *host_prob);
+
+/* Measure the k <= 6 qubits of mask: the outcome is chosen from the
+ * sv_marginals probabilities by the inverse cumulative distribution with the
+ * caller's uniform u in [0, 1) (the first outcome, in outcome order, whose
+ * cumulative probability exceeds u times the total), then the state
+ * collapses onto it as by sv_collapse.  *host_value receives the outcome as
+ * bits at the mask positions, *host_prob (may be NULL) its probability. */
+int sv_measure(sv_handle h, uint64_t mask, double u, uint64_t *host_value, double *host_prob);
+
+/* Sec. 2.4: n_samples full-register outcomes drawn from p_x = |psi_x|^2
+ * without changing the state (repeated measurement of one prepared state).
+ * Outcome s is the first x, in index order, whose FP64 cumulative
+ * probability exceeds uniforms[s] times the total.  uniforms: n_samples host
+ * doubles in [0, 1); host_out: n_samples host uint64.  0 <= n_samples <= 2^24.
+ * The cumulative sums are formed per block of amplitudes, so an outcome can
+ * differ from a strictly sequential sum only when the target falls within
+ * rounding of a boundary between outcomes. */
+int sv_sample(sv_handle h, int n_samples, const double *uniforms, uint64_t *host_out);
+
+/* Adjoint-method gradient of L/* Adjoint-method gradient of L = <psi| H |psi>, H = sum_j coeffs[j] Z^{z_masks[j]},
  * psi = U_G ... U_1 psi_0 for the gate list ops with angles params.
  * On entry h must hold the circuit's output psi (as left by sv_run with the
  * same ops and params); lam is a second handle of the same size and dtype

@@ -10,7 +10,7 @@ There is no CPU fallback: without the built library every call raises.
 from __future__ import annotations
 
 import ctypes
-from typing import Iterable, Optional, Sequence
+from typing import Iterable, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -117,6 +117,37 @@ def sv_expectation(h, z_masks: Sequence[int], coeffs: Sequence[float]) -> float:
     out = ctypes.c_double()
     _lib.check(_lib.load().sv_expectation(h, len(m), _u64ptr(m), _dptr(c), ctypes.byref(out)))
     return out.value
+
+
+def sv_marginals(h, mask: int) -> np.ndarray:
+    """FP64 outcome probabilities of the qubits of mask (at most 6)."""
+    out = np.empty(1 << bin(mask).count("1"), np.float64)
+    _lib.check(_lib.load().sv_marginals(h, mask, _dptr(out)))
+    return out
+
+
+def sv_collapse(h, mask: int, value: int) -> float:
+    """Project onto (x & mask) == (value & mask) and renormalise; returns the probability."""
+    p = ctypes.c_double()
+    _lib.check(_lib.load().sv_collapse(h, mask, value, ctypes.byref(p)))
+    return p.value
+
+
+def sv_measure(h, mask: int, u: float) -> Tuple[int, float]:
+    """Measure the qubits of mask with the uniform u in [0, 1); the state
+    collapses.  Returns (outcome bits at the mask positions, probability)."""
+    v = ctypes.c_uint64()
+    p = ctypes.c_double()
+    _lib.check(_lib.load().sv_measure(h, mask, u, ctypes.byref(v), ctypes.byref(p)))
+    return int(v.value), p.value
+
+
+def sv_sample(h, uniforms) -> np.ndarray:
+    """Full-register outcomes for the given uniforms in [0, 1); state unchanged."""
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    out = np.empty(len(u), np.uint64)
+    _lib.check(_lib.load().sv_sample(h, len(u), _dptr(u), _u64ptr(out)))
+    return out
 
 
 SV_OP_DTYPE = np.dtype([("kind", np.int32), ("n_targets", np.int32), ("targets", np.int32, (2,)),
@@ -325,6 +356,18 @@ class State:
 
     def expectation(self, z_masks, coeffs) -> float:
         return sv_expectation(self.handle, z_masks, coeffs)
+
+    def marginals(self, mask: int) -> np.ndarray:
+        return sv_marginals(self.handle, mask)
+
+    def collapse(self, mask: int, value: int) -> float:
+        return sv_collapse(self.handle, mask, value)
+
+    def measure(self, mask: int, u: float) -> Tuple[int, float]:
+        return sv_measure(self.handle, mask, u)
+
+    def sample(self, uniforms) -> np.ndarray:
+        return sv_sample(self.handle, uniforms)
 
     def sync(self) -> "State":
         sv_sync(self.handle)

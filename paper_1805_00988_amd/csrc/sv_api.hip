@@ -65,10 +65,10 @@ static int hip_fail(hipError_t e, const char *where) {
 
 // ----------------------------------------------------------- launch timing
 enum KernelId { K_INIT, K_GATE1, K_GATE2, K_SCALE, K_TILE, K_PROBS, K_EXPECT, K_FUSED, K_ADJOINT,
-                K_COUNT };
+                K_MEASURE, K_COUNT };
 static const char *kKernelNames[K_COUNT] = {"init_basis", "gate1_stream", "gate2_stream",
                                             "scale_subspace", "tile_pass", "probabilities",
-                                            "expectation", "fused_block", "adjoint_step"};
+                                            "expectation", "fused_block", "adjoint_step", "measurement"};
 
 static hipEvent_t take_event(sv_state *h) {
     if (h->pool_used == h->pool.size()) {
@@ -1419,6 +1419,154 @@ int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const doub
                           hipMemcpyDeviceToHost, h->stream));
     SV_HIP(hipStreamSynchronize(h->stream));
     *host_out = h->h_result[0];
+    return SV_OK;
+}
+
+// ============================================================ measurement
+static int measure_positions(const sv_state *h, uint64_t mask, MeasurePos *mp) {
+    if (mask == 0) return fail(SV_EINVAL, "empty qubit mask");
+    if (h->n < 64 && (mask >> h->n) != 0) return fail(SV_EINVAL, "qubit mask has bits >= n");
+    const int k = __builtin_popcountll(mask);
+    if (k > kMaxMeasureQubits) return fail(SV_EINVAL, "at most 6 qubits per measurement");
+    mp->k = 0;
+    for (uint64_t m = mask; m; m &= m - 1) mp->pos[mp->k++] = __builtin_ctzll(m);
+    return SV_OK;
+}
+
+// FP64 outcome probabilities of the qubits in mp, in outcome order.
+static int marginals_of(sv_state *h, const MeasurePos &mp, std::vector<double> &out) {
+    const int G = marginal_blocks(h->n, h->dtype), nb = 1 << mp.k;
+    int rc = ensure_scratch(h, (size_t)nb * G + nb);
+    if (rc) return rc;
+    {
+        Timed tm(h, K_MEASURE, state_bytes(h), 2.0 * (double)(1ull << h->n));
+        SV_HIP(launch_marginals(h->amps, h->n, h->dtype, mp, h->d_scratch, h->stream));
+    }
+    SV_HIP(launch_sum_slots(h->d_scratch, nb, G, h->d_scratch + (size_t)nb * G, h->stream));
+    out.assign(nb, 0.0);
+    SV_HIP(hipMemcpyAsync(out.data(), h->d_scratch + (size_t)nb * G, nb * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+    return SV_OK;
+}
+
+static int collapse_onto(sv_state *h, uint64_t mask, uint64_t want, double p) {
+    Timed tm(h, K_MEASURE, 2.0 * state_bytes(h), 2.0 * (double)(1ull << h->n));
+    SV_HIP(launch_collapse(h->amps, h->n, h->dtype, mask, want, 1.0 / std::sqrt(p), h->stream));
+    return SV_OK;
+}
+
+int sv_marginals(sv_handle h, uint64_t mask, double *host_out) {
+    if (!h || !host_out) return fail(SV_EINVAL, "NULL argument");
+    MeasurePos mp{};
+    int rc = measure_positions(h, mask, &mp);
+    if (rc) return rc;
+    std::vector<double> m;
+    if ((rc = marginals_of(h, mp, m))) return rc;
+    std::memcpy(host_out, m.data(), m.size() * sizeof(double));
+    return SV_OK;
+}
+
+int sv_collapse(sv_handle h, uint64_t mask, uint64_t value, double *host_prob) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (h->n < 64 && (mask >> h->n) != 0) return fail(SV_EINVAL, "qubit mask has bits >= n");
+    const uint64_t want = value & mask;
+    const int G = marginal_blocks(h->n, h->dtype);
+    int rc = ensure_scratch(h, (size_t)G + 1);
+    if (rc) return rc;
+    {
+        Timed tm(h, K_MEASURE, state_bytes(h), 2.0 * (double)(1ull << h->n));
+        SV_HIP(launch_masked_prob(h->amps, h->n, h->dtype, mask, want, h->d_scratch, h->stream));
+    }
+    SV_HIP(launch_sum_slots(h->d_scratch, 1, G, h->d_scratch + G, h->stream));
+    double p = 0.0;
+    SV_HIP(hipMemcpyAsync(&p, h->d_scratch + G, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+    if (host_prob) *host_prob = p;
+    if (!(p > 0.0)) return fail(SV_EINVAL, "the outcome has probability 0");
+    return collapse_onto(h, mask, want, p);
+}
+
+int sv_measure(sv_handle h, uint64_t mask, double u, uint64_t *host_value, double *host_prob) {
+    if (!h || !host_value) return fail(SV_EINVAL, "NULL argument");
+    if (!(u >= 0.0 && u < 1.0)) return fail(SV_EINVAL, "u must be in [0, 1)");
+    MeasurePos mp{};
+    int rc = measure_positions(h, mask, &mp);
+    if (rc) return rc;
+    std::vector<double> m;
+    if ((rc = marginals_of(h, mp, m))) return rc;
+    // inverse CDF over the outcomes in index order
+    double total = 0.0;
+    for (double x : m) total += x;
+    if (!(total > 0.0)) return fail(SV_EINVAL, "the state has norm 0");
+    const double t = u * total;
+    double c = 0.0;
+    int o = -1, last = 0;
+    for (int i = 0; i < (int)m.size(); ++i) {
+        c += m[i];
+        if (m[i] > 0.0) last = i;
+        if (c > t) {
+            o = i;
+            break;
+        }
+    }
+    if (o < 0) o = last;
+    uint64_t v = 0;
+    for (int i = 0; i < mp.k; ++i)
+        if ((o >> i) & 1) v |= 1ull << mp.pos[i];
+    *host_value = v;
+    if (host_prob) *host_prob = m[o];
+    return collapse_onto(h, mask, v, m[o]);
+}
+
+int sv_sample(sv_handle h, int n_samples, const double *uniforms, uint64_t *host_out) {
+    if (!h) return fail(SV_EINVAL, "NULL handle");
+    if (n_samples < 0 || n_samples > (1 << 24)) return fail(SV_EINVAL, "n_samples must be in [0, 2^24]");
+    if (n_samples == 0) return SV_OK;
+    if (!uniforms || !host_out) return fail(SV_EINVAL, "NULL argument");
+    for (int i = 0; i < n_samples; ++i)
+        if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return fail(SV_EINVAL, "uniforms must be in [0, 1)");
+    const int bl = sample_block_log(h->n);
+    const size_t B = (size_t)1 << (h->n - bl), S = (size_t)n_samples;
+    int rc = ensure_scratch(h, B + 3 * S);
+    if (rc) return rc;
+    double *d_sums = h->d_scratch;
+    int64_t *d_blk = reinterpret_cast<int64_t *>(h->d_scratch + B);
+    double *d_tgt = h->d_scratch + B + S;
+    uint64_t *d_out = reinterpret_cast<uint64_t *>(h->d_scratch + B + 2 * S);
+    {
+        Timed tm(h, K_MEASURE, state_bytes(h), 2.0 * (double)(1ull << h->n));
+        SV_HIP(launch_block_sums(h->amps, h->n, h->dtype, bl, d_sums, h->stream));
+    }
+    std::vector<double> sums(B), pre(B + 1);
+    SV_HIP(hipMemcpyAsync(sums.data(), d_sums, B * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+    pre[0] = 0.0;
+    for (size_t b = 0; b < B; ++b) pre[b + 1] = pre[b] + sums[b];
+    const double total = pre[B];
+    if (!(total > 0.0)) return fail(SV_EINVAL, "the state has norm 0");
+    // block of each sample: the first block whose cumulative end exceeds the
+    // target (the last block with mass if rounding leaves none)
+    size_t last_nz = 0;
+    for (size_t b = 0; b < B; ++b)
+        if (sums[b] > 0.0) last_nz = b;
+    std::vector<int64_t> blk(S);
+    std::vector<double> tgt(S);
+    for (size_t i = 0; i < S; ++i) {
+        const double t = uniforms[i] * total;
+        size_t b = (size_t)(std::upper_bound(pre.begin() + 1, pre.end(), t) - (pre.begin() + 1));
+        if (b >= B) b = last_nz;
+        blk[i] = (int64_t)b;
+        tgt[i] = t - pre[b];
+    }
+    SV_HIP(hipMemcpyAsync(d_blk, blk.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+    SV_HIP(hipMemcpyAsync(d_tgt, tgt.data(), S * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    {
+        Timed tm(h, K_MEASURE, 0.0, 0.0);
+        SV_HIP(launch_sample_scan(h->amps, h->dtype, bl, n_samples, d_blk, d_tgt, d_out, h->stream));
+    }
+    SV_HIP(hipMemcpyAsync(host_out, d_out, S * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
     return SV_OK;
 }
 

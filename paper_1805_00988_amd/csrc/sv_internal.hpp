@@ -198,6 +198,28 @@ struct BatchArgs {
 hipError_t launch_batch(const BatchArgs &args, int dtype, int sweep_w, int tile_m, int grid,
                         hipStream_t s);
 
+// ----------------------------------------------------------- measurement
+constexpr int kMaxMeasureQubits = 6;
+struct MeasurePos {
+    int k;                        // measured qubits
+    int pos[kMaxMeasureQubits];   // ascending; outcome bit i = qubit pos[i]
+};
+int marginal_blocks(int n, int dtype);
+// partials[b * marginal_blocks + g]: workgroup g's sum of outcome b
+hipError_t launch_marginals(const void *amps, int n, int dtype, const MeasurePos &mp, double *partials,
+                            hipStream_t s);
+// partials[g], marginal_blocks workgroups: sum of |psi_x|^2 over (x & mask) == want
+hipError_t launch_masked_prob(const void *amps, int n, int dtype, uint64_t mask, uint64_t want,
+                              double *partials, hipStream_t s);
+// psi_x *= (x & mask) == want ? scale : 0
+hipError_t launch_collapse(void *amps, int n, int dtype, uint64_t mask, uint64_t want, double scale,
+                           hipStream_t s);
+// sampling: blocks of 2^sample_block_log(n) amplitudes
+int sample_block_log(int n);
+hipError_t launch_block_sums(const void *amps, int n, int dtype, int block_log, double *sums, hipStream_t s);
+hipError_t launch_sample_scan(const void *amps, int dtype, int block_log, int n_samples, const int64_t *blk,
+                              const double *target, uint64_t *out, hipStream_t s);
+
 int adjoint_blocks();
 hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int n_terms,
                                const uint64_t *masks, const double *coeffs, double *partials,
