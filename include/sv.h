@@ -214,7 +214,7 @@ int sv_measure(sv_handle h, uint64_t mask, double u, uint64_t *host_value, doubl
  * rounding of a boundary between outcomes. */
 int sv_sample(sv_handle h, int n_samples, const double *uniforms, uint64_t *host_out);
 
-/* Adjoint-method gradient of L/* Adjoint-method gradient of L = <psi| H |psi>, H = sum_j coeffs[j] Z^{z_masks[j]},
+/* Adjoint-method gradient of L = <psi| H |psi>, H = sum_j coeffs[j] Z^{z_masks[j]},
  * psi = U_G ... U_1 psi_0 for the gate list ops with angles params.
  * On entry h must hold the circuit's output psi (as left by sv_run with the
  * same ops and params); lam is a second handle of the same size and dtype

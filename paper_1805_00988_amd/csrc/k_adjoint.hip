@@ -140,14 +140,16 @@ int adjoint_tile_qubits(int dtype) { return dtype == SV_C64 ? 12 : 11; } // 2 x 
 
 template <typename T, int W, int P>
 __device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
-                                            const uint32_t (&li)[1 << W], const TileGate &G, uint32_t cin) {
+                                            const GroupBits<W> &g, const TileGate &G, uint32_t cin) {
     constexpr int D = 1 << W;
     const cpx<T> m0 = gmat<T>(G, 0), m1 = gmat<T>(G, 1), m2 = gmat<T>(G, 2), m3 = gmat<T>(G, 3);
+    const uint32_t cr = cin & g.fall;
     double acc = 0.0;
+    if (!lane_controls(g, cin)) return acc;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (j & (1 << P)) continue;
-        if ((li[j] & cin) != cin) continue;
+        if ((g.F[j] & cr) != cr) continue;
         const int c = j | (1 << P);
         const cpx<T> z0 = cfma(m0, v[j], cmul(m1, v[c]));
         const cpx<T> z1 = cfma(m2, v[j], cmul(m3, v[c]));
@@ -158,7 +160,7 @@ __device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx
 
 template <typename T, int W>
 __device__ __forceinline__ double probe_gate(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
-                                             const uint32_t (&li)[1 << W], const TileGate &G) {
+                                             const GroupBits<W> &li, const TileGate &G) {
     const int p = G.b0;
     const uint32_t cin = G.cin;
     if (p == 0) return probe_pos<T, W, 0>(v, w, li, G, cin);
@@ -215,10 +217,12 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                 }
                 const uint32_t pg = lds_phys<T>(gb);
                 cpx<T> v[D], w[D];
-                uint32_t li[D];
+                GroupBits<W> li;
+                li.gb = gb;
+                li.fall = F[D - 1];
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    li[j] = gb | F[j];
+                    li.F[j] = F[j];
                     v[j] = lp[pg ^ PF[j]];
                     w[j] = ll[pg ^ PF[j]];
                 }

@@ -854,8 +854,8 @@ static std::vector<std::complex<double>> pad_matrix(const std::vector<std::compl
     return P;
 }
 
-// Shortest contiguous run (low tile qubits) of a fused pass: 1 KiB.
-static int fused_lmin(const sv_state *h) { return std::min(h->n, h->dtype == SV_C64 ? 7 : 6); }
+// Shortest contiguous run (low tile qubits) of a fused pass: 512 bytes.
+static int fused_lmin(const sv_state *h) { return std::min(h->n, h->dtype == SV_C64 ? 6 : 5); }
 
 // One fused pass over the blocks bs[idx] (all their qubits fit in one tile).
 // Blocks run on the matrix cores in the requested precision (the state's own

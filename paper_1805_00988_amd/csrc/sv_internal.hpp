@@ -158,7 +158,6 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
                              const DenseBlock *dev_blocks, int n_blocks, const char *dev_base, int prec,
                              hipStream_t s);
 int fused_tile_qubits(int dtype);
-
 hipError_t launch_probabilities(const void *amps, int n, int dtype, void *dev_out,
                                 double *dev_partials, int n_partials, double *dev_total,
                                 hipStream_t s);

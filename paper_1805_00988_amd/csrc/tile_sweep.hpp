@@ -162,34 +162,32 @@ __device__ __forceinline__ void swap_regs(cpx<T> &a, cpx<T> &b) {
     swap_f(a.re, b.re);
     swap_f(a.im, b.im);
 }
-// Conditional exchange: a ^= d, b ^= d with d = (a ^ b) masked by the condition.
-template <typename U>
-__device__ __forceinline__ void xswap(U &a, U &b, U mask) {
-    const U d = (a ^ b) & mask;
-    a ^= d;
-    b ^= d;
-}
-template <typename T>
-__device__ __forceinline__ void swap_if(cpx<T> &a, cpx<T> &b, bool cond) {
-    using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
-    const U mask = cond ? ~(U)0 : (U)0;
-    U ar = __builtin_bit_cast(U, a.re), ai = __builtin_bit_cast(U, a.im);
-    U br = __builtin_bit_cast(U, b.re), bi = __builtin_bit_cast(U, b.im);
-    xswap(ar, br, mask);
-    xswap(ai, bi, mask);
-    a = cpx<T>{__builtin_bit_cast(T, ar), __builtin_bit_cast(T, ai)};
-    b = cpx<T>{__builtin_bit_cast(T, br), __builtin_bit_cast(T, bi)};
-}
+// The local index of amplitude j of a group is gb | F[j]: gb holds the
+// group's own tile bits (per lane), F[j] the bits of register index j at the
+// sweep's positions (wave-uniform).  Every test of tile bits therefore splits
+// into one per-lane test of gb per gate and a uniform test of F[j] per
+// amplitude; gates without controls inside the tile compile the tests out.
+template <int W>
+struct GroupBits {
+    uint32_t gb;
+    uint32_t F[1 << W];
+    uint32_t fall; // all register position bits
+};
 
-// The local index of amplitude j of a group is gb | F[j] (gb: the group's
-// bits, F[j]: j's bits deposited at the sweep's register positions, uniform).
-// Control tests are compiled out for gates without controls inside the tile.
+// Per-lane part of a control test: the control bits outside the registers.
+template <int W>
+__device__ __forceinline__ bool lane_controls(const GroupBits<W> &g, uint32_t cin) {
+    const uint32_t cg = cin & ~g.fall;
+    return (g.gb & cg) == cg;
+}
 
 // Gate on register position P of a group of 2^W (pairs j, j | 2^P).
 template <typename T, int W, int P, bool CHECK>
-__device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&li)[1 << W],
-                                         const TileGate &G, int kind, uint32_t cin) {
+__device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const GroupBits<W> &g, const TileGate &G,
+                                         int kind, uint32_t cin) {
     constexpr int D = 1 << W;
+    const uint32_t cr = cin & g.fall;
+    if (CHECK && !lane_controls(g, cin)) return;
     // Every output first collects the terms that do not read its own input
     // component, then takes that component in one final FMA: the input dies
     // at its last use and the result can stay in the same register.
@@ -198,7 +196,7 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&l
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (j & (1 << P)) continue;
-            if (CHECK && (li[j] & cin) != cin) continue;
+            if (CHECK && (g.F[j] & cr) != cr) continue;
             const int c = j | (1 << P);
             const cpx<T> x0 = v[j], x1 = v[c];
             const T a_re = fma(g1.re, x1.re, fma(-g1.im, x1.im, -g0.im * x0.im));
@@ -213,7 +211,7 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&l
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (j & (1 << P)) continue;
-            if (CHECK && (li[j] & cin) != cin) continue;
+            if (CHECK && (g.F[j] & cr) != cr) continue;
             const int c = j | (1 << P);
             const cpx<T> x0 = v[j], x1 = v[c];
             const T a_re = r1 * x1.re, a_im = r1 * x1.im, b_re = r2 * x0.re, b_im = r2 * x0.im;
@@ -224,21 +222,22 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const uint32_t (&l
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (j & (1 << P)) continue;
-            const int c = j | (1 << P);
-            if (CHECK) swap_if(v[j], v[c], (li[j] & cin) == cin);
-            else swap_regs(v[j], v[c]);
+            if (CHECK && (g.F[j] & cr) != cr) continue;
+            swap_regs(v[j], v[j | (1 << P)]);
         }
     }
 }
 
 template <typename T, int W, int P, int Q, bool CHECK>
-__device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], const uint32_t (&li)[1 << W],
-                                         const TileGate &G, uint32_t cin) {
+__device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], const GroupBits<W> &g, const TileGate &G,
+                                         uint32_t cin) {
     constexpr int D = 1 << W;
+    const uint32_t cr = cin & g.fall;
+    if (CHECK && !lane_controls(g, cin)) return;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (j & ((1 << P) | (1 << Q))) continue;
-        if (CHECK && (li[j] & cin) != cin) continue;
+        if (CHECK && (g.F[j] & cr) != cr) continue;
         const int idx[4] = {j, j | (1 << P), j | (1 << Q), j | (1 << P) | (1 << Q)};
         cpx<T> x[4], a[4];
 #pragma unroll
@@ -261,34 +260,42 @@ __device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], const uint32_t (&l
     }
 }
 
+// diag(d0, d1) on tile bit b0.  On a register position the factor of each
+// amplitude is a uniform choice; on a group bit it is one choice per lane.
 template <typename T, int W, bool CHECK>
-__device__ __forceinline__ void sweep_diag(cpx<T> (&v)[1 << W], const uint32_t (&li)[1 << W],
-                                           const TileGate &G, uint32_t cin) {
+__device__ __forceinline__ void sweep_diag(cpx<T> (&v)[1 << W], const GroupBits<W> &g, const TileGate &G,
+                                           uint32_t cin) {
     constexpr int D = 1 << W;
     const cpx<T> d0 = gmat<T>(G, 0), d1 = gmat<T>(G, 1);
     const uint32_t bm = 1u << G.b0;
+    const uint32_t cr = cin & g.fall;
     const bool d0_one = d0.re == T(1) && d0.im == T(0);
-    if (d0_one) { // phase gate: only amplitudes with the target bit set change
+    if (CHECK && !lane_controls(g, cin)) return;
+    if (bm & g.fall) {
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const uint32_t l = li[j];
-            if (CHECK && (l & cin) != cin) continue;
-            if (l & bm) cmul_inplace(v[j], d1);
+            if (CHECK && (g.F[j] & cr) != cr) continue;
+            const bool up = (g.F[j] & bm) != 0;
+            if (d0_one) {
+                if (up) cmul_inplace(v[j], d1);
+            } else {
+                cmul_inplace(v[j], up ? d1 : d0);
+            }
         }
     } else {
+        const bool up = (g.gb & bm) != 0;
+        if (d0_one && !up) return; // phase gate: only amplitudes with the bit set change
+        const cpx<T> d{up ? d1.re : d0.re, up ? d1.im : d0.im}; // component-wise select
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const uint32_t l = li[j];
-            if (CHECK && (l & cin) != cin) continue;
-            const bool up = (l & bm) != 0; // component-wise select keeps d0, d1 in registers
-            cmul_inplace(v[j], cpx<T>{up ? d1.re : d0.re, up ? d1.im : d0.im});
+            if (CHECK && (g.F[j] & cr) != cr) continue;
+            cmul_inplace(v[j], d);
         }
     }
 }
 
 template <typename T, int W, bool CHECK>
-__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], const uint32_t (&li)[1 << W],
-                                             const TileGate &G) {
+__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], const GroupBits<W> &li, const TileGate &G) {
     const int kind = G.kind;
     const uint32_t cin = G.cin;
     if (kind == SK_DIAG) {
@@ -351,10 +358,12 @@ __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSwe
             }
             const uint32_t pg = lds_phys<T>(gb);
             cpx<T> v[D];
-            uint32_t li[D];
+            GroupBits<W> li;
+            li.gb = gb;
+            li.fall = F[D - 1];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                li[j] = gb | F[j];
+                li.F[j] = F[j];
                 v[j] = lds[pg ^ PF[j]];
             }
             for (int gi = 0; gi < ng; ++gi) {
