@@ -94,10 +94,11 @@ __global__ __launch_bounds__(256) void k_dense_native(typename Amp16<T>::type *v
 // ------------------------------------------------------------ matrix cores
 // All matrix-core kernels share one addressing scheme.  A wave-tile is ROWS
 // groups (MFMA rows) of one block; the group index of row i of wave-tile wt
-// is wt*ROWS + i, and its LDS offset is goff[wt*ROWS] ^ goff[i] since the two
-// parts have disjoint bits.  So every A-operand and result address is a
-// per-lane constant (set once per block) XOR a wave-uniform table entry,
-// read through the scalar cache.
+// is wt*ROWS + i, and its LDS offset is goff_hi[wt] ^ goff_lo[i] since the
+// two parts have disjoint bits (the host stores qoff[2^K], goff_lo[ROWS],
+// goff_hi[groups / ROWS] consecutively).  So every A-operand and result
+// address is a per-lane constant (set once per block) XOR a wave-uniform
+// table entry.
 //
 // Operand fragments (host-built, per lane, in the MFMA B-operand order):
 //   split-BF16: frag[((part * KS + s) * 2 + hl) * 64 + lane]   (bf16x8)
@@ -127,7 +128,7 @@ __device__ __forceinline__ void split4(const cpx<float> (&x)[4], bf16x8 &h, bf16
 }
 
 // complex64, split-BF16 (3 products, FP32 accumulate).  K = 4: 16x16x32,
-// one K-step; K = 5: 32x32x16, four K-steps.  Threads: 512 (K = 4), 256 (K = 5).
+// one K-step; K = 5: 32x32x16, four K-steps.
 template <int K>
 struct Bf16Cfg;
 template <>
@@ -139,80 +140,61 @@ struct Bf16Cfg<5> {
     static constexpr int rows = 32, ksteps = 4, threads = 256;
 };
 
+// One block applied to the tile in LDS by this wave's wave-tiles.  f, qoff,
+// goff (goff_lo then goff_hi) point to the block's operand and tables.
 template <int K>
-__global__ __launch_bounds__(Bf16Cfg<K>::threads) void k_dense_bf16(float4 *v, TileSpec sp, int m,
-                                                                    const DenseBlock *__restrict__ blocks,
-                                                                    int n_blocks, const char *__restrict__ base_ptr,
-                                                                    uint64_t n_tiles) {
+__device__ __forceinline__ void block_bf16(cpx<float> *lds, const bf16x8 *f, const uint32_t *qoff,
+                                           const uint32_t *goff, uint32_t n_wt, int wave, int nwaves) {
     using C = Bf16Cfg<K>;
-    constexpr int D = 1 << K, ROWS = C::rows, KS = C::ksteps;
+    constexpr int ROWS = C::rows, KS = C::ksteps;
     constexpr int ACC = ROWS == 32 ? 16 : 4;
     using accT = typename std::conditional<ROWS == 32, floatx16, floatx4>::type;
-    extern __shared__ char lds_raw[];
-    cpx<float> *lds = reinterpret_cast<cpx<float> *>(lds_raw);
-    const uint32_t tsize = 1u << m;
-    const uint32_t n_wt = (tsize >> K) / ROWS;
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    const int nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int r = lane % ROWS, kk = lane / ROWS;
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t base = tile_base(sp, tile);
-        tile_load<float, Bf16Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
-        for (int b = 0; b < n_blocks; ++b) {
-            const DenseBlock &B = blocks[b];
-            const uint32_t *__restrict__ qoff = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
-            const uint32_t *__restrict__ goff = qoff + D;
-            const bf16x8 *f = reinterpret_cast<const bf16x8 *>(base_ptr + B.op_off);
-            bf16x8 bw[2][KS][2];
+    bf16x8 bw[2][KS][2];
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int s = 0; s < KS; ++s)
+        for (int s = 0; s < KS; ++s)
 #pragma unroll
-                    for (int hl = 0; hl < 2; ++hl) bw[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
-            // lane (r, kk) reads amplitudes 8s + 4kk + i of row r; holds result
-            // rows 4kk + q (16x16) or 8(q/4) + 4kk + q%4 (32x32) of column r
-            const uint32_t a_lane = goff[r] ^ qoff[4 * kk];
-            const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
-            for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-                const uint32_t gw = goff[wt * ROWS];
-                const uint32_t pa = gw ^ a_lane;
-                accT yr = {}, yi = {};
+            for (int hl = 0; hl < 2; ++hl) bw[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
+    // lane (r, kk) reads amplitudes 8s + 4kk + i of row r; holds result
+    // rows 4kk + q (16x16) or 8(q/4) + 4kk + q%4 (32x32) of column r
+    const uint32_t a_lane = goff[r] ^ qoff[4 * kk];
+    const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
+    for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
+        const uint32_t gw = goff[ROWS + wt]; // goff_hi[wt]
+        const uint32_t pa = gw ^ a_lane;
+        accT yr = {}, yi = {};
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    cpx<float> x[4];
+        for (int s = 0; s < KS; ++s) {
+            cpx<float> x[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) x[i] = lds[pa ^ qoff[8 * s + i]];
-                    bf16x8 h, l;
-                    split4(x, h, l);
-                    if constexpr (ROWS == 32) {
-                        yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][0], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][0], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][1], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][1], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[0][s][0], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[1][s][0], yi, 0, 0, 0);
-                    } else {
-                        yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][0], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][0], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][1], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][1], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[0][s][0], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[1][s][0], yi, 0, 0, 0);
-                    }
-                }
-                const uint32_t po = gw ^ o_lane;
-#pragma unroll
-                for (int q = 0; q < ACC; ++q) {
-                    const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
-                    lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
-                }
+            for (int i = 0; i < 4; ++i) x[i] = lds[pa ^ qoff[8 * s + i]];
+            bf16x8 h, l;
+            split4(x, h, l);
+            if constexpr (ROWS == 32) {
+                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][0], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][0], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][1], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][1], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[0][s][0], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[1][s][0], yi, 0, 0, 0);
+            } else {
+                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][0], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][0], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][1], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][1], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[0][s][0], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[1][s][0], yi, 0, 0, 0);
             }
-            __syncthreads();
         }
-        tile_store<float, Bf16Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
+        const uint32_t po = gw ^ o_lane;
+#pragma unroll
+        for (int q = 0; q < ACC; ++q) {
+            const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
+            lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
+        }
     }
 }
 
@@ -232,68 +214,47 @@ struct F32Cfg<5> {
 };
 
 template <int K>
-__global__ __launch_bounds__(F32Cfg<K>::threads) void k_dense_f32(float4 *v, TileSpec sp, int m,
-                                                                  const DenseBlock *__restrict__ blocks,
-                                                                  int n_blocks, const char *__restrict__ base_ptr,
-                                                                  uint64_t n_tiles) {
+__device__ __forceinline__ void block_f32(cpx<float> *lds, const float *f, const uint32_t *qoff,
+                                          const uint32_t *goff, uint32_t n_wt, int wave, int nwaves) {
     using C = F32Cfg<K>;
     constexpr int D = 1 << K, ROWS = C::rows, KPS = C::kps;
     constexpr int KS = 2 * D / KPS, HALF = KS / 2;
     constexpr int ACC = ROWS == 32 ? 16 : 4;
     using accT = typename std::conditional<ROWS == 32, floatx16, floatx4>::type;
-    extern __shared__ char lds_raw[];
-    cpx<float> *lds = reinterpret_cast<cpx<float> *>(lds_raw);
-    const uint32_t tsize = 1u << m;
-    const uint32_t n_wt = (tsize >> K) / ROWS;
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    const int nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int r = lane % ROWS, kk = lane / ROWS;
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t base = tile_base(sp, tile);
-        tile_load<float, F32Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
-        for (int b = 0; b < n_blocks; ++b) {
-            const DenseBlock &B = blocks[b];
-            const uint32_t *__restrict__ qoff = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
-            const uint32_t *__restrict__ goff = qoff + D;
-            const float *f = reinterpret_cast<const float *>(base_ptr + B.op_off);
-            float bw[2][KS];
+    float bw[2][KS];
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int s = 0; s < KS; ++s) bw[p][s] = f[(p * KS + s) * 64 + lane];
-            const uint32_t a_lane = goff[r] ^ qoff[kk];
-            const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
-            for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-                const uint32_t gw = goff[wt * ROWS];
-                const uint32_t pa = gw ^ a_lane;
-                accT yr = {}, yi = {};
+        for (int s = 0; s < KS; ++s) bw[p][s] = f[(p * KS + s) * 64 + lane];
+    const uint32_t a_lane = goff[r] ^ qoff[kk];
+    const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
+    for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
+        const uint32_t gw = goff[ROWS + wt]; // goff_hi[wt]
+        const uint32_t pa = gw ^ a_lane;
+        accT yr = {}, yi = {};
 #pragma unroll
-                for (int s = 0; s < HALF; ++s) {
-                    const cpx<float> x = lds[pa ^ qoff[KPS * s]];
-                    if constexpr (ROWS == 32) {
-                        yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[0][s], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[1][s], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
-                    } else {
-                        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[0][s], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[1][s], yi, 0, 0, 0);
-                        yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
-                        yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
-                    }
-                }
-                const uint32_t po = gw ^ o_lane;
-#pragma unroll
-                for (int q = 0; q < ACC; ++q) {
-                    const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
-                    lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
-                }
+        for (int s = 0; s < HALF; ++s) {
+            const cpx<float> x = lds[pa ^ qoff[KPS * s]];
+            if constexpr (ROWS == 32) {
+                yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[0][s], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[1][s], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
+            } else {
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[0][s], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[1][s], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
             }
-            __syncthreads();
         }
-        tile_store<float, F32Cfg<K>::threads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
+        const uint32_t po = gw ^ o_lane;
+#pragma unroll
+        for (int q = 0; q < ACC; ++q) {
+            const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
+            lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
+        }
     }
 }
 
@@ -301,71 +262,99 @@ __global__ __launch_bounds__(F32Cfg<K>::threads) void k_dense_f32(float4 *v, Til
 // out as the FP32 16x16x4 ones, result element q of lane l is row 4q + l/16,
 // column l%16, as measured on the device): wave-tiles of 16 groups, D/16
 // output tiles of 16 amplitudes per part, K-steps as in the FP32 kernel.
-// Fragments stay in registers for K = 4 and are read per K-step (L1) for K = 5.
+// Fragments stay in registers for K = 4 and are read per K-step for K = 5.
 template <int K>
-__global__ __launch_bounds__(256) void k_dense_f64(double2 *v, TileSpec sp, int m,
-                                                   const DenseBlock *__restrict__ blocks, int n_blocks,
-                                                   const char *__restrict__ base_ptr, uint64_t n_tiles) {
+__device__ __forceinline__ void block_f64(cpx<double> *lds, const double *frag, const uint32_t *qoff,
+                                          const uint32_t *goff, uint32_t n_wt, int wave, int nwaves) {
     constexpr int D = 1 << K;
     constexpr int NT = D / 16;
     constexpr int KS = 2 * D / 4;
     constexpr int HALF = KS / 2;
     constexpr bool PRELOAD = K == 4;
-    extern __shared__ char lds_raw[];
-    cpx<double> *lds = reinterpret_cast<cpx<double> *>(lds_raw);
-    const uint32_t tsize = 1u << m;
-    const uint32_t n_wt = (tsize >> K) / 16;
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    const int nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int r = lane & 15, kk = lane >> 4;
+    double bpre[PRELOAD ? 2 * NT * KS : 1];
+    if constexpr (PRELOAD) {
+#pragma unroll
+        for (int i = 0; i < 2 * NT * KS; ++i) bpre[i] = frag[i * 64 + lane];
+    }
+    const uint32_t a_lane = goff[r] ^ qoff[kk];
+    const uint32_t o_lane = goff[kk] ^ qoff[r];
+    for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
+        const uint32_t gw = goff[16 + wt]; // goff_hi[wt]
+        const uint32_t pa = gw ^ a_lane;
+        doublex4 acc[2][NT];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[p][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < HALF; ++s) {
+            const cpx<double> x = lds[pa ^ qoff[4 * s]];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int i0 = (p * NT + nt) * KS + s, i1 = i0 + HALF;
+                    const double b0 = PRELOAD ? bpre[PRELOAD ? i0 : 0] : frag[i0 * 64 + lane];
+                    const double b1 = PRELOAD ? bpre[PRELOAD ? i1 : 0] : frag[i1 * 64 + lane];
+                    acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, b0, acc[p][nt], 0, 0, 0);
+                    acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, b1, acc[p][nt], 0, 0, 0);
+                }
+        }
+        const uint32_t po = gw ^ o_lane;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                lds[po ^ goff[4 * q] ^ qoff[16 * nt]] = cpx<double>{acc[0][nt][q], acc[1][nt][q]};
+    }
+}
+
+// Register-staged passes (any tile size; the only path for K = 5): each
+// workgroup loads a tile, applies the blocks, stores it.  ENG: SV_PREC_FP32,
+// SV_PREC_SPLIT_BF16 (complex64) or kPrecMfma64 (complex128).
+template <int ENG, int K>
+struct EngCfg {
+    using T = typename std::conditional<ENG == kPrecMfma64, double, float>::type;
+    static constexpr int rows = ENG == kPrecMfma64 ? 16 : (K == 5 ? 32 : 16);
+    static constexpr int threads = ENG == kPrecMfma64 ? 256 : (K == 5 ? 256 : 512);
+};
+
+template <int ENG, int K>
+__device__ __forceinline__ void apply_block(cpx<typename EngCfg<ENG, K>::T> *lds, const char *op,
+                                            const uint32_t *tab, uint32_t n_wt, int wave, int nwaves) {
+    const uint32_t *qoff = tab, *goff = tab + (1 << K);
+    if constexpr (ENG == SV_PREC_SPLIT_BF16)
+        block_bf16<K>(lds, reinterpret_cast<const bf16x8 *>(op), qoff, goff, n_wt, wave, nwaves);
+    else if constexpr (ENG == SV_PREC_FP32)
+        block_f32<K>(lds, reinterpret_cast<const float *>(op), qoff, goff, n_wt, wave, nwaves);
+    else
+        block_f64<K>(lds, reinterpret_cast<const double *>(op), qoff, goff, n_wt, wave, nwaves);
+}
+
+template <int ENG, int K>
+__global__ __launch_bounds__((EngCfg<ENG, K>::threads)) void k_dense_mfma(
+    typename Amp16<typename EngCfg<ENG, K>::T>::type *v, TileSpec sp, int m, const DenseBlock *__restrict__ blocks,
+    int n_blocks, const char *__restrict__ base_ptr, uint64_t n_tiles) {
+    using Cf = EngCfg<ENG, K>;
+    using T = typename Cf::T;
+    extern __shared__ char lds_raw[];
+    cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
+    const uint32_t tsize = 1u << m;
+    const uint32_t n_wt = (tsize >> K) / Cf::rows;
+    const int wave = wave_id(), nwaves = Cf::threads / 64;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
-        tile_load<double, 256, 8>(v, lds, sp, base, tsize);
+        tile_load<T, Cf::threads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
-            const uint32_t *__restrict__ qoff = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
-            const uint32_t *__restrict__ goff = qoff + D;
-            const double *frag = reinterpret_cast<const double *>(base_ptr + B.op_off);
-            double bpre[PRELOAD ? 2 * NT * KS : 1];
-            if constexpr (PRELOAD) {
-#pragma unroll
-                for (int i = 0; i < 2 * NT * KS; ++i) bpre[i] = frag[i * 64 + lane];
-            }
-            const uint32_t a_lane = goff[r] ^ qoff[kk];
-            const uint32_t o_lane = goff[kk] ^ qoff[r];
-            for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-                const uint32_t gw = goff[wt * 16u];
-                const uint32_t pa = gw ^ a_lane;
-                doublex4 acc[2][NT];
-#pragma unroll
-                for (int p = 0; p < 2; ++p)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[p][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < HALF; ++s) {
-                    const cpx<double> x = lds[pa ^ qoff[4 * s]];
-#pragma unroll
-                    for (int p = 0; p < 2; ++p)
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) {
-                            const int i0 = (p * NT + nt) * KS + s, i1 = i0 + HALF;
-                            const double b0 = PRELOAD ? bpre[PRELOAD ? i0 : 0] : frag[i0 * 64 + lane];
-                            const double b1 = PRELOAD ? bpre[PRELOAD ? i1 : 0] : frag[i1 * 64 + lane];
-                            acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, b0, acc[p][nt], 0, 0, 0);
-                            acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, b1, acc[p][nt], 0, 0, 0);
-                        }
-                }
-                const uint32_t po = gw ^ o_lane;
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        lds[po ^ goff[4 * q] ^ qoff[16 * nt]] = cpx<double>{acc[0][nt][q], acc[1][nt][q]};
-            }
+            apply_block<ENG, K>(lds, base_ptr + B.op_off, reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off),
+                                n_wt, wave, nwaves);
             __syncthreads();
         }
-        tile_store<double, 256, 8>(v, lds, sp, base, tsize);
+        tile_store<T, Cf::threads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
 }
@@ -381,35 +370,26 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1024);
-    if (prec == kPrecMfma64) {
-        if (dtype != SV_C128 || k < 4 || ((1u << m) >> k) % 16) return hipErrorInvalidValue;
-        if (k == 4) {
-            (void)hipFuncSetAttribute((const void *)k_dense_f64<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
-            k_dense_f64<4><<<grid, 256, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks, dev_base, n_tiles);
-        } else {
-            (void)hipFuncSetAttribute((const void *)k_dense_f64<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
-            k_dense_f64<5><<<grid, 256, lds, s>>>((double2 *)amps, sp, m, dev_blocks, n_blocks, dev_base, n_tiles);
-        }
-        return hipGetLastError();
-    }
     if (prec != SV_PREC_NATIVE) {
-        if (dtype != SV_C64 || k < 4) return hipErrorInvalidValue;
-        const int rows = k == 5 ? 32 : 16;
+        const bool f64 = prec == kPrecMfma64;
+        if (f64 != (dtype == SV_C128) || k < 4) return hipErrorInvalidValue;
+        const int rows = (!f64 && k == 5) ? 32 : 16;
         if (((1u << m) >> k) % rows) return hipErrorInvalidValue; // whole wave-tiles only
-#define SV_MFMA_CASE(KERN, KK, THREADS)                                                            \
-    {                                                                                              \
-        (void)hipFuncSetAttribute((const void *)KERN<KK>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                  (int)lds);                                                       \
-        KERN<KK><<<grid, THREADS, lds, s>>>((float4 *)amps, sp, m, dev_blocks, n_blocks, dev_base,  \
-                                            n_tiles);                                              \
+#define SV_MFMA_CASE(ENG, KK)                                                                      \
+    if (prec == ENG && k == KK) {                                                                  \
+        using VT = typename Amp16<typename EngCfg<ENG, KK>::T>::type;                              \
+        (void)hipFuncSetAttribute((const void *)k_dense_mfma<ENG, KK>,                             \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+        k_dense_mfma<ENG, KK><<<grid, EngCfg<ENG, KK>::threads, lds, s>>>((VT *)amps, sp, m, dev_blocks, \
+                                                                         n_blocks, dev_base, n_tiles); \
         return hipGetLastError();                                                                  \
     }
-        if (prec == SV_PREC_SPLIT_BF16 && k == 4) SV_MFMA_CASE(k_dense_bf16, 4, Bf16Cfg<4>::threads)
-        if (prec == SV_PREC_SPLIT_BF16 && k == 5) SV_MFMA_CASE(k_dense_bf16, 5, Bf16Cfg<5>::threads)
-        if (prec == SV_PREC_FP32 && k == 4) SV_MFMA_CASE(k_dense_f32, 4, F32Cfg<4>::threads)
-        if (prec == SV_PREC_FP32 && k == 5) SV_MFMA_CASE(k_dense_f32, 5, F32Cfg<5>::threads)
+        SV_MFMA_CASE(SV_PREC_SPLIT_BF16, 4)
+        SV_MFMA_CASE(SV_PREC_SPLIT_BF16, 5)
+        SV_MFMA_CASE(SV_PREC_FP32, 4)
+        SV_MFMA_CASE(SV_PREC_FP32, 5)
+        SV_MFMA_CASE(kPrecMfma64, 4)
+        SV_MFMA_CASE(kPrecMfma64, 5)
 #undef SV_MFMA_CASE
         return hipErrorInvalidValue;
     }

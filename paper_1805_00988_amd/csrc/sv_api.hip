@@ -832,10 +832,17 @@ static size_t dense_frag_bytes(const sv_state *h, int k, int engine) {
     return align256(((size_t)1 << (2 * k)) * (h->dtype == SV_C64 ? 8 : 16));
 }
 
-// operand plus, for the matrix cores, the LDS offset tables (qoff, goff)
+// MFMA rows (groups per wave-tile) of an engine at block width k
+static int mfma_rows(int k, int engine) { return engine == kPrecMfma64 ? 16 : (k == 5 ? 32 : 16); }
+
+// operand plus, for the matrix cores, the LDS offset tables
+// (qoff[2^k], goff_lo[rows], goff_hi[2^(m-k) / rows])
 static size_t dense_op_bytes(const sv_state *h, int k, int m, int engine) {
     size_t b = dense_frag_bytes(h, k, engine);
-    if (is_mfma(engine)) b += align256((((size_t)1 << k) + ((size_t)1 << (m - k))) * sizeof(uint32_t));
+    if (is_mfma(engine)) {
+        const size_t rows = (size_t)mfma_rows(k, engine);
+        b += align256((((size_t)1 << k) + rows + (((size_t)1 << (m - k)) / rows)) * sizeof(uint32_t));
+    }
     return b;
 }
 
@@ -949,7 +956,7 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
 static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
     const size_t fb = dense_frag_bytes(h, fp.k, fp.engine);
     const size_t ob = dense_op_bytes(h, fp.k, fp.m, fp.engine);
-    const int sw = lds_swizzle_bits(h->dtype == SV_C64 ? 8 : 16);
+    const int ab = h->dtype == SV_C64 ? 8 : 16;
     size_t opo = off + align256(fp.blocks.size() * sizeof(DenseBlock));
     for (size_t b = 0; b < fp.blocks.size(); ++b, opo += ob) {
         DenseBlock &db = fp.blocks[b];
@@ -984,9 +991,12 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
                     if ((x >> i) & 1u) r |= 1u << pos[i];
                 return r;
             };
-            for (uint32_t j = 0; j < (1u << fp.k); ++j) qoff[j] = lds_swizzle(deposit(j, db.bp.qpos, fp.k), sw);
-            for (uint32_t g = 0; g < (1u << (fp.m - fp.k)); ++g)
-                goff[g] = lds_swizzle(deposit(g, db.bp.gpos, db.bp.ng), sw);
+            const uint32_t rows = (uint32_t)mfma_rows(fp.k, fp.engine);
+            uint32_t *ghi = goff + rows;
+            for (uint32_t j = 0; j < (1u << fp.k); ++j) qoff[j] = lds_swizzle(deposit(j, db.bp.qpos, fp.k), ab);
+            for (uint32_t g = 0; g < rows; ++g) goff[g] = lds_swizzle(deposit(g, db.bp.gpos, db.bp.ng), ab);
+            for (uint32_t w = 0; w < (1u << (fp.m - fp.k)) / rows; ++w)
+                ghi[w] = lds_swizzle(deposit(w * rows, db.bp.gpos, db.bp.ng), ab);
         }
     }
     std::memcpy(h->h_arena + off, fp.blocks.data(), fp.blocks.size() * sizeof(DenseBlock));

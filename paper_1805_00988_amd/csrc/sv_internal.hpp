@@ -98,14 +98,15 @@ struct TileSweep {
     int32_t pad[3];
 };
 
-// LDS swizzle of a tile index: the low sw bits (one 128-byte LDS row of
-// amplitudes) are XOR-ed with a fold of the higher bits.  Linear over XOR.
-__host__ __device__ inline uint32_t lds_swizzle(uint32_t l, int sw) {
+// LDS swizzle of a tile index, linear over XOR (and its own inverse): the
+// positions within one 128-byte LDS row (16 complex64 or 8 complex128
+// amplitudes) are XOR-ed with a fold of the row index, so lanes whose
+// amplitudes differ in arbitrary tile bits spread over the banks.
+__host__ __device__ inline uint32_t lds_swizzle(uint32_t l, int amp_bytes) {
+    const int sw = amp_bytes == 8 ? 4 : 3;
     const uint32_t f = (l >> sw) ^ (l >> (2 * sw)) ^ (l >> (3 * sw));
     return l ^ (f & ((1u << sw) - 1u));
 }
-// swizzle width for amplitudes of 'amp_bytes' bytes (8: complex64, 16: complex128)
-__host__ __device__ constexpr int lds_swizzle_bits(int amp_bytes) { return amp_bytes == 8 ? 4 : 3; }
 
 constexpr int kMaxTileHigh = 8; // extra tile qubits beyond the low block
 struct TileSpec {
@@ -143,9 +144,10 @@ struct BlockPos {
 };
 // tab_off: byte offset of the block's LDS offset tables (matrix cores only):
 // uint32 qoff[2^k] = swizzled LDS offset of matrix index j deposited at
-// qpos, then goff[2^(m-k)] = the same for group index g deposited at gpos.
-// Both maps are linear over XOR, so the offset of (group g, index j) is
-// goff[g] ^ qoff[j] and tables of disjoint index parts combine by XOR.
+// qpos, then goff_lo[R] and goff_hi[2^(m-k) / R] = the same for group index
+// g (g < R) and g = w * R deposited at gpos, R the kernel's MFMA rows.  The
+// maps are linear over XOR, so the offset of (group w*R + i, index j) is
+// goff_hi[w] ^ goff_lo[i] ^ qoff[j].
 struct DenseBlock {
     BlockPos bp;
     int32_t pad;

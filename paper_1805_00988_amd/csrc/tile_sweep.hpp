@@ -8,10 +8,10 @@
 // in registers, applies the sweep's gates in order and writes them back, so
 // the tile crosses LDS once per sweep instead of once per gate.
 //
-// LDS addresses are swizzled: the low bits of the index (one 128-byte LDS
-// row: 16 complex64 or 8 complex128 amplitudes) are XOR-ed with a fold of the
-// higher bits, so the lanes of a wave, whose groups differ in arbitrary tile
-// bits, spread over the banks.
+// LDS addresses are swizzled (lds_swizzle): positions within one 128-byte
+// LDS row (16 complex64 or 8 complex128 amplitudes) are XOR-ed with a fold of
+// the row index, so the lanes of a wave, whose groups differ in arbitrary
+// tile bits, spread over the banks.
 #pragma once
 
 #include "sv_internal.hpp"
@@ -21,7 +21,7 @@ namespace sv {
 
 template <typename T>
 __device__ __forceinline__ uint32_t lds_phys(uint32_t l) {
-    return lds_swizzle(l, lds_swizzle_bits(2 * sizeof(T)));
+    return lds_swizzle(l, 2 * (int)sizeof(T));
 }
 
 // ------------------------------------------------------------ tile staging
