@@ -26,6 +26,10 @@ HIPCC_FLAGS = [
     # packed-FP32 instructions are kept out of all generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # uniform (scalar) branches are left unstructured: the sweep kernels'
+    # per-gate dispatch then merges its paths without copying the register
+    # group held across it
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     # per-kernel register / scratch / occupancy report (parsed into _build/)
     "-Rpass-analysis=kernel-resource-usage",
 ]

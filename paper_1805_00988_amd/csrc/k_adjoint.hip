@@ -140,16 +140,15 @@ int adjoint_tile_qubits(int dtype) { return dtype == SV_C64 ? 12 : 11; } // 2 x 
 
 template <typename T, int W, int P>
 __device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
-                                            const GroupBits<W> &g, const TileGate &G, uint32_t cin) {
+                                            uint32_t gb, const TileGate &G) {
     constexpr int D = 1 << W;
     const cpx<T> m0 = gmat<T>(G, 0), m1 = gmat<T>(G, 1), m2 = gmat<T>(G, 2), m3 = gmat<T>(G, 3);
-    const uint32_t cr = cin & g.fall;
     double acc = 0.0;
-    if (!lane_controls(g, cin)) return acc;
+    if ((gb & G.lane) != G.lane) return acc;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (j & (1 << P)) continue;
-        if ((g.F[j] & cr) != cr) continue;
+        if (!((G.amask >> j) & 1u)) continue;
         const int c = j | (1 << P);
         const cpx<T> z0 = cfma(m0, v[j], cmul(m1, v[c]));
         const cpx<T> z1 = cfma(m2, v[j], cmul(m3, v[c]));
@@ -160,17 +159,16 @@ __device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx
 
 template <typename T, int W>
 __device__ __forceinline__ double probe_gate(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
-                                             const GroupBits<W> &li, const TileGate &G) {
+                                             uint32_t gb, const TileGate &G) {
     const int p = G.b0;
-    const uint32_t cin = G.cin;
-    if (p == 0) return probe_pos<T, W, 0>(v, w, li, G, cin);
-    if constexpr (W >= 2) if (p == 1) return probe_pos<T, W, 1>(v, w, li, G, cin);
-    if constexpr (W >= 3) if (p == 2) return probe_pos<T, W, 2>(v, w, li, G, cin);
-    if constexpr (W >= 4) if (p == 3) return probe_pos<T, W, 3>(v, w, li, G, cin);
+    if (p == 0) return probe_pos<T, W, 0>(v, w, gb, G);
+    if constexpr (W >= 2) if (p == 1) return probe_pos<T, W, 1>(v, w, gb, G);
+    if constexpr (W >= 3) if (p == 2) return probe_pos<T, W, 2>(v, w, gb, G);
+    if constexpr (W >= 4) if (p == 3) return probe_pos<T, W, 3>(v, w, gb, G);
     return 0.0;
 }
 
-template <typename T, int W>
+template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::type *psi, typename AV<T>::type *lam,
                                                       TileSpec sp, int m, const TileSweep *__restrict__ sweeps,
                                                       int n_sweeps, const TileGate *__restrict__ gates,
@@ -194,52 +192,31 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
         for (int si = 0; si < n_sweeps; ++si) {
             const TileSweep &S = sweeps[si];
             const int ng = S.n_gates;
-            uint32_t F[D], PF[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                uint32_t f = 0;
-#pragma unroll
-                for (int b = 0; b < W; ++b)
-                    if ((j >> b) & 1) f |= 1u << S.qpos[b];
-                F[j] = f;
-                PF[j] = lds_phys<T>(f);
-            }
+            uint32_t PF[D];
+            register_offsets<T, W>(S, PF);
             // every lane runs the same number of iterations (the probe's wave
             // reduction needs all 64 lanes); lanes past the last group add 0
             for (uint32_t g0 = 0; g0 < n_groups; g0 += blockDim.x) {
                 const uint32_t g = g0 + threadIdx.x;
                 const bool act = g < n_groups;
-                uint32_t gb = act ? g : 0u;
-#pragma unroll
-                for (int b = 0; b < W; ++b) {
-                    const uint32_t low = (1u << S.qpos[b]) - 1u;
-                    gb = (gb & low) | ((gb & ~low) << 1);
-                }
+                const uint32_t gb = group_bits<W>(S, act ? g : 0u);
                 const uint32_t pg = lds_phys<T>(gb);
                 cpx<T> v[D], w[D];
-                GroupBits<W> li;
-                li.gb = gb;
-                li.fall = F[D - 1];
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    li.F[j] = F[j];
                     v[j] = lp[pg ^ PF[j]];
                     w[j] = ll[pg ^ PF[j]];
                 }
                 for (int gi = 0; gi < ng; ++gi) {
                     const TileGate &G = gates[goff + gi];
-                    if ((base & G.cout) != G.cout) continue; // uniform
                     if (G.kind == SK_PARAM) {
-                        const double mine = act ? probe_gate<T, W>(v, w, li, G) : 0.0;
+                        if ((base & G.cout) != G.cout) continue; // uniform
+                        const double mine = act ? probe_gate<T, W>(v, w, gb, G) : 0.0;
                         const double c = wave_sum_d(mine);
                         if ((threadIdx.x & 63) == 0) atomicAdd(&slot_acc[G.b1], c);
-
-                    } else if (G.cin == 0) {
-                        sweep_gate_t<T, W, false>(v, li, G);
-                        sweep_gate_t<T, W, false>(w, li, G);
                     } else {
-                        sweep_gate_t<T, W, true>(v, li, G);
-                        sweep_gate_t<T, W, true>(w, li, G);
+                        sweep_gate_t<T, W, TWOQ>(v, gb, G, record_mask(G, base));
+                        sweep_gate_t<T, W, TWOQ>(w, gb, G, record_mask(G, base));
                     }
                 }
                 if (act) {
@@ -263,7 +240,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
 
 hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,
                                const TileSweep *dev_sweeps, int n_sweeps, const TileGate *dev_gates,
-                               int slot0, int n_slots, double *partials, int n_blocks, hipStream_t s) {
+                               int slot0, int n_slots, double *partials, int n_blocks, bool two_qubit,
+                               hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
     if (m > n || m > adjoint_tile_qubits(dtype) || spec.L < vbits || n_slots > kMaxAdjSlots || m < 1)
@@ -274,11 +252,19 @@ hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const Til
     const int W = std::min(m, sweep_width(dtype));
 #define SV_ADJ_CASE(TT, VT, WW)                                                                    \
     if (W == WW) {                                                                                 \
-        (void)hipFuncSetAttribute((const void *)k_adjoint_tile<TT, WW>,                            \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
-        k_adjoint_tile<TT, WW><<<n_blocks, 256, lds, s>>>((VT *)psi, (VT *)lam, spec, m, dev_sweeps,\
-                                                          n_sweeps, dev_gates, slot0, n_slots,     \
-                                                          partials, n_tiles);                      \
+        if (two_qubit) {                                                                           \
+            (void)hipFuncSetAttribute((const void *)k_adjoint_tile<TT, WW, true>,                  \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+            k_adjoint_tile<TT, WW, true><<<n_blocks, 256, lds, s>>>(                               \
+                (VT *)psi, (VT *)lam, spec, m, dev_sweeps, n_sweeps, dev_gates, slot0, n_slots,    \
+                partials, n_tiles);                                                                \
+        } else {                                                                                   \
+            (void)hipFuncSetAttribute((const void *)k_adjoint_tile<TT, WW, false>,                 \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+            k_adjoint_tile<TT, WW, false><<<n_blocks, 256, lds, s>>>(                              \
+                (VT *)psi, (VT *)lam, spec, m, dev_sweeps, n_sweeps, dev_gates, slot0, n_slots,    \
+                partials, n_tiles);                                                                \
+        }                                                                                          \
         return hipGetLastError();                                                                  \
     }
     if (dtype == SV_C64) {

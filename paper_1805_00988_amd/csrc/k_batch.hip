@@ -14,6 +14,7 @@
 #include "tile_sweep.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace sv {
 
@@ -52,7 +53,7 @@ __device__ __forceinline__ double zterm(cpx<T> a, uint64_t x, uint64_t zmask) {
     return (__popcll(x & zmask) & 1) ? -p : p;
 }
 
-template <typename T, int W>
+template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
     using V = BV<T>;
     extern __shared__ char lds_raw[];
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
                     }
                 }
                 __syncthreads();
-                tile_run_sweeps<T, W>(lds, m, base, a.sweeps + p.sweep_off, p.n_sweeps,
+                tile_run_sweeps<T, W, TWOQ>(lds, m, base, a.sweeps + p.sweep_off, p.n_sweeps,
                                       a.gates + p.gate_off);
                 if (last) {
                     for (uint32_t l = threadIdx.x; l < tsize; l += kBatchThreads)
@@ -135,24 +136,33 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
 
 __global__ void k_batch_reset(unsigned int *counter) { *counter = 0u; }
 
-template <typename T, int W>
+template <typename T, int W, bool TWOQ>
 static void launch_batch_t(const BatchArgs &args, int grid, size_t lds, hipStream_t s) {
-    (void)hipFuncSetAttribute((const void *)k_batch<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_batch<T, W, TWOQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    k_batch<T, W><<<grid, kBatchThreads, lds, s>>>(args);
+    k_batch<T, W, TWOQ><<<grid, kBatchThreads, lds, s>>>(args);
 }
 
-hipError_t launch_batch(const BatchArgs &args, int dtype, int sweep_w, int tile_m, int grid,
+hipError_t launch_batch(const BatchArgs &args, int dtype, int sweep_w, int tile_m, int grid, bool two_qubit,
                         hipStream_t s) {
     const int m = tile_m;
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     k_batch_reset<<<1, 1, 0, s>>>(args.counter);
-    if (dtype == SV_C64 && sweep_w == 4) launch_batch_t<float, 4>(args, grid, lds, s);
-    else if (dtype == SV_C64 && sweep_w == 3) launch_batch_t<float, 3>(args, grid, lds, s);
-    else if (dtype == SV_C128 && sweep_w == 3) launch_batch_t<double, 3>(args, grid, lds, s);
-    else if (dtype == SV_C128 && sweep_w == 4) launch_batch_t<double, 4>(args, grid, lds, s);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+#define SV_BATCH_CASE(TT, WW, Q)                                                                   \
+    if ((dtype == SV_C64) == std::is_same<TT, float>::value && sweep_w == WW && two_qubit == Q) {  \
+        launch_batch_t<TT, WW, Q>(args, grid, lds, s);                                             \
+        return hipGetLastError();                                                                  \
+    }
+    SV_BATCH_CASE(float, 4, false)
+    SV_BATCH_CASE(float, 3, false)
+    SV_BATCH_CASE(double, 3, false)
+    SV_BATCH_CASE(double, 4, false)
+    SV_BATCH_CASE(float, 4, true)
+    SV_BATCH_CASE(float, 3, true)
+    SV_BATCH_CASE(double, 3, true)
+    SV_BATCH_CASE(double, 4, true)
+#undef SV_BATCH_CASE
+    return hipErrorInvalidValue;
 }
 
 } // namespace sv

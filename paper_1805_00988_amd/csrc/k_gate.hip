@@ -368,7 +368,7 @@ __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t bas
     return g;
 }
 
-template <typename T, int W>
+template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v, TileSpec sp, int m,
                                                        const TileSweep *__restrict__ sweeps, int n_sweeps,
                                                        const TileGate *__restrict__ gates,
@@ -382,24 +382,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v,
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
         tile_load<T, kTileThreads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
-        tile_run_sweeps<T, W>(lds, m, base, sweeps, n_sweeps, gates);
+        tile_run_sweeps<T, W, TWOQ>(lds, m, base, sweeps, n_sweeps, gates);
         tile_store<T, kTileThreads, 8>(v, lds, sp, base, tsize);
         __syncthreads();
     }
     (void)sizeof(V);
 }
 
-template <typename T, int W>
+template <typename T, int W, bool TWOQ>
 static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m, const TileSweep *sw,
                           int n_sweeps, const TileGate *g, uint64_t n_tiles, size_t lds, hipStream_t s) {
-    (void)hipFuncSetAttribute((const void *)k_tile<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_tile<T, W, TWOQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 2048);
-    k_tile<T, W><<<grid, kTileThreads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles);
+    k_tile<T, W, TWOQ><<<grid, kTileThreads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles);
 }
 
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const TileGate *dev_gates, hipStream_t s) {
+                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
     if (m > n || m > tile_max_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh || m < 1)
@@ -407,20 +407,24 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     const int W = std::min(m, sweep_width(dtype));
-#define SV_TILE_CASE(WW)                                                                           \
-    if (W == WW) {                                                                                 \
+#define SV_TILE_CASE(WW, Q)                                                                        \
+    if (W == WW && two_qubit == Q) {                                                               \
         if (dtype == SV_C64)                                                                       \
-            launch_tile_t<float, WW>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,     \
-                                     n_tiles, lds, s);                                             \
+            launch_tile_t<float, WW, Q>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,  \
+                                        n_tiles, lds, s);                                          \
         else                                                                                       \
-            launch_tile_t<double, WW>((double2 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,   \
-                                      n_tiles, lds, s);                                            \
+            launch_tile_t<double, WW, Q>((double2 *)amps, spec, m, dev_sweeps, n_sweeps,           \
+                                         dev_gates, n_tiles, lds, s);                              \
         return hipGetLastError();                                                                  \
     }
-    SV_TILE_CASE(4)
-    SV_TILE_CASE(3)
-    SV_TILE_CASE(2)
-    SV_TILE_CASE(1)
+    SV_TILE_CASE(4, false)
+    SV_TILE_CASE(3, false)
+    SV_TILE_CASE(2, false)
+    SV_TILE_CASE(1, false)
+    SV_TILE_CASE(4, true)
+    SV_TILE_CASE(3, true)
+    SV_TILE_CASE(2, true)
+    SV_TILE_CASE(1, true)
 #undef SV_TILE_CASE
     return hipErrorInvalidValue;
 }

@@ -297,6 +297,7 @@ struct PassCode {
     TileSpec sp{};
     int m = 0;
     double flops_per_amp = 0.0; // algorithmic flops of the pass per state amplitude
+    bool two_qubit = false;     // holds SK_2Q records
     std::vector<TileSweep> sweeps;
     std::vector<TileGate> gates;
     size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + gates.size() * sizeof(TileGate); }
@@ -309,13 +310,39 @@ static bool is_x(const Gate &g) {
     return g.k == 1 && std::memcmp(g.U, x, sizeof(x)) == 0;
 }
 
-static void encode_controls(const TileSpec &sp, uint64_t ctrl, TileGate *r) {
+// Controls of a gate: bits outside the tile go to the record (tested once
+// per tile on its base index); the local bits inside the tile are returned.
+static uint32_t encode_controls(const TileSpec &sp, uint64_t ctrl, TileGate *r) {
+    uint32_t cin = 0;
     for (uint64_t c = ctrl; c; c &= c - 1) {
         const int b = __builtin_ctzll(c);
         const int lb = local_bit(sp, b);
-        if (lb >= 0) r->cin |= 1u << lb;
+        if (lb >= 0) cin |= 1u << lb;
         else r->cout |= 1ull << b;
     }
+    return cin;
+}
+
+// Tile bits of register index j of a sweep over the local positions qset.
+static uint32_t register_bits(const std::vector<int> &qset, int j) {
+    uint32_t f = 0;
+    for (size_t b = 0; b < qset.size(); ++b)
+        if ((j >> b) & 1) f |= 1u << qset[b];
+    return f;
+}
+
+// Split the in-tile controls cin of a record into the per-lane part and the
+// register-index mask: amask gets every j with no bit of 'skip' set (the low
+// index of a pair or quad), with 'need' set, and whose register bits hold
+// the register controls.
+static void encode_sweep_masks(const std::vector<int> &qset, uint32_t cin, uint32_t skip, uint32_t need,
+                               TileGate *r) {
+    const uint32_t fall = register_bits(qset, (1 << qset.size()) - 1);
+    const uint32_t cr = cin & fall;
+    r->lane = cin & ~fall;
+    r->amask = 0;
+    for (int j = 0; j < (1 << qset.size()); ++j)
+        if (!(j & skip) && (j & need) == need && (register_bits(qset, j) & cr) == cr) r->amask |= 1u << j;
 }
 
 // Store n complex entries (re, im interleaved, FP64) in the record in the
@@ -349,7 +376,7 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
                                   bool f32) {
     TileGate r;
     std::memset(&r, 0, sizeof(r));
-    encode_controls(sp, g.ctrl, &r);
+    const uint32_t cin = encode_controls(sp, g.ctrl, &r);
     auto pos = [&](int q) {
         const int lb = local_bit(sp, q);
         for (size_t j = 0; j < qset.size(); ++j)
@@ -358,16 +385,28 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
     };
     if (is_diag1(g)) {
         const double d[4] = {g.U[0], g.U[1], g.U[6], g.U[7]};
-        r.kind = SK_DIAG;
-        r.b0 = local_bit(sp, g.t[0]);
+        const int p = pos(g.t[0]);
         put_matrix(r, d, 2, f32);
+        if (p >= 0) {
+            // on a register position: a phase gate (d0 = 1) leaves the
+            // amplitudes with the target bit clear alone
+            r.kind = SK_DIAGR;
+            r.b0 = p;
+            encode_sweep_masks(qset, cin, 0, is_one(g.U) ? 1u << p : 0u, &r);
+        } else {
+            r.kind = SK_DIAG;
+            r.b0 = local_bit(sp, g.t[0]);
+            encode_sweep_masks(qset, cin, 0, 0, &r);
+        }
         return r;
     }
     if (g.k == 1) {
         r.b0 = pos(g.t[0]);
         bool real = true;
         for (int i = 0; i < 4; ++i) real = real && g.U[2 * i + 1] == 0.0;
-        r.kind = is_x(g) ? SK_SWAP : (real ? SK_REAL : SK_GEN);
+        encode_sweep_masks(qset, cin, 1u << r.b0, 0, &r);
+        // an exchange with per-lane controls runs as the real matrix X
+        r.kind = is_x(g) && r.lane == 0 ? SK_SWAP : (real ? SK_REAL : SK_GEN);
         put_matrix(r, g.U, 4, f32);
         return r;
     }
@@ -390,6 +429,7 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
             }
         put_matrix(r, u, 16, f32);
     }
+    encode_sweep_masks(qset, cin, (1u << r.b0) | (1u << r.b1), 0, &r);
     return r;
 }
 
@@ -407,11 +447,12 @@ static TileGate encode_probe(const TileSpec &sp, const std::vector<int> &qset, c
                              bool f32) {
     TileGate r;
     std::memset(&r, 0, sizeof(r));
-    encode_controls(sp, g.ctrl, &r);
+    const uint32_t cin = encode_controls(sp, g.ctrl, &r);
     r.kind = SK_PARAM;
     const int lb = local_bit(sp, g.t[0]);
     r.b0 = (int)(std::find(qset.begin(), qset.end(), lb) - qset.begin());
     r.b1 = pr.slot;
+    encode_sweep_masks(qset, cin, 1u << r.b0, 0, &r);
     put_matrix(r, pr.M, 4, f32);
     return r;
 }
@@ -445,6 +486,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
                 pc.flops_per_amp += 8.0 / (double)(1ull << __builtin_popcountll(gs[i]->ctrl));
             }
             pc.gates.push_back(encode_sweep_gate(sp, qset, *gs[i], f32));
+            pc.two_qubit = pc.two_qubit || pc.gates.back().kind == SK_2Q;
             ++sw.n_gates;
             pc.flops_per_amp += (probes ? 2.0 : 1.0) * gate_flops_per_amp(*gs[i]);
         }
@@ -487,7 +529,7 @@ static int launch_pass(sv_state *h, const PassCode &pc, size_t off) {
     const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + off +
                                                             align256(pc.sweeps.size() * sizeof(TileSweep)));
     Timed tm(h, K_TILE, 2.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
-    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, h->stream));
+    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, pc.two_qubit, h->stream));
     return SV_OK;
 }
 
@@ -1172,6 +1214,7 @@ struct sv_batch {
     std::vector<int64_t> state_off;
     std::vector<int> n_passes;
     int tile_m = 0, sweep_w = 0, grid = 0;
+    bool two_qubit = false; // the program holds SK_2Q records
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -1234,8 +1277,9 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
     b->tile_m = tile_m;
     b->sweep_w = sweep_w;
     b->grid = grid;
+    b->two_qubit = std::any_of(bp.gates.begin(), bp.gates.end(), [](const TileGate &r) { return r.kind == SK_2Q; });
     // one eager launch (sets kernel attributes, checks the launch), then capture
-    SV_HIP(launch_batch(a, b->dtype, sweep_w, tile_m, grid, b->stream));
+    SV_HIP(launch_batch(a, b->dtype, sweep_w, tile_m, grid, b->two_qubit, b->stream));
     SV_HIP(hipStreamSynchronize(b->stream));
     // capture on a private stream (the caller's may be the null stream, which
     // cannot be captured); the graph is launched on the caller's stream
@@ -1246,7 +1290,7 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
         (void)hipStreamDestroy(cap);
         return hip_fail(e0, "hipStreamBeginCapture");
     }
-    hipError_t e = launch_batch(a, b->dtype, sweep_w, tile_m, grid, cap);
+    hipError_t e = launch_batch(a, b->dtype, sweep_w, tile_m, grid, b->two_qubit, cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     (void)hipStreamDestroy(cap);
@@ -1816,7 +1860,7 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, con
                                                                 align256(pc.sweeps.size() * sizeof(TileSweep)));
         Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
         hipError_t e = launch_adjoint_tile(h->amps, lam->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt,
-                                           slot0[pi], nslot[pi], partials + loss_n, B, h->stream);
+                                           slot0[pi], nslot[pi], partials + loss_n, B, pc.two_qubit, h->stream);
         if (e != hipSuccess) return restore(hip_fail(e, "launch_adjoint_tile"));
     }
     hipError_t e = launch_sum_slots(partials, 1, (int)loss_n, sums, h->stream);

@@ -74,18 +74,28 @@ __device__ __forceinline__ uint64_t expand(const Enum &e, uint64_t i) {
 // among the sweep's register qubits, except for SK_DIAG, where b0 is the
 // target's local bit.
 enum SweepKind : int32_t {
-    SK_GEN = 1,  // general 2x2 on sweep position b0
-    SK_REAL = 2, // real 2x2 (m[0], m[2], m[4], m[6] hold the entries)
-    SK_DIAG = 3, // diag(d0, d1) on tile bit b0 (any position); m: d0, d1
-    SK_SWAP = 4, // X: exchange the pair
-    SK_2Q = 5,   // 4x4 on sweep positions b0 < b1 (bit 0 of the matrix index <-> b0)
-    SK_PARAM = 6 // adjoint sweep: add Im<lam|M|psi> for M (entries 0-3) on position b0
-                 // to slot b1; the undo of the gate follows as its own record
+    SK_GEN = 1,   // general 2x2 on sweep position b0
+    SK_REAL = 2,  // real 2x2 (m[0], m[2], m[4], m[6] hold the entries)
+    SK_DIAG = 3,  // diag(d0, d1) on tile bit b0 outside the registers; m: d0, d1
+    SK_SWAP = 4,  // X: exchange the pair (never with per-lane controls)
+    SK_2Q = 5,    // 4x4 on sweep positions b0 < b1 (bit 0 of the matrix index <-> b0)
+    SK_PARAM = 6, // adjoint sweep: add Im<lam|M|psi> for M (entries 0-3) on position b0
+                  // to slot b1; the undo of the gate follows as its own record
+    SK_DIAGR = 7  // diag(d0, d1) on sweep position b0; m: d0, d1
 };
+// Controls inside the tile are split by where they sit in the sweep: bits
+// on tile positions outside the registers ('lane') are constant over one
+// lane's group and tested per lane; bits on register positions only select
+// register indices and are folded, with the gate's own pattern, into
+// 'amask': bit j is set for every register index j the record starts an
+// update at (the low index of each pair or quad whose controls hold; for a
+// diagonal gate every amplitude whose factor can differ from 1).
 struct TileGate {
     int32_t kind;
     int32_t b0, b1;
-    uint32_t cin;      // control bits inside the tile (local positions)
+    uint32_t lane;     // control bits on tile positions outside the registers
+    uint32_t amask;    // register indices updated (see above)
+    uint32_t pad;
     uint64_t cout;     // control bits outside the tile (global positions)
     double m[32];      // matrix entries, complex interleaved: FP64, or FP32 packed into
                        // the first half of the storage for complex64 states
@@ -128,8 +138,9 @@ hipError_t launch_gate2(void *amps, int n, int dtype, int t0, int t1, uint64_t c
                         const double *U, hipStream_t s);
 hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const double *factor,
                         hipStream_t s);
+// two_qubit: the pass holds SK_2Q records (selects the kernel instance with that path)
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const TileGate *dev_gates, hipStream_t s);
+                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, hipStream_t s);
 int tile_max_qubits(int dtype);
 int sweep_width(int dtype);
 // Dense blocks of a fused tile pass: positions of the block's qubits in the
@@ -196,7 +207,7 @@ struct BatchArgs {
     int n_circuits;
     uint64_t zmask;
 };
-hipError_t launch_batch(const BatchArgs &args, int dtype, int sweep_w, int tile_m, int grid,
+hipError_t launch_batch(const BatchArgs &args, int dtype, int sweep_w, int tile_m, int grid, bool two_qubit,
                         hipStream_t s);
 
 // ----------------------------------------------------------- measurement
@@ -232,7 +243,8 @@ hipError_t launch_sum_slots(const double *partials, int n_slots, int n_blocks, d
 // written to partials[(slot0 + i) * n_blocks + workgroup] for i < n_slots.
 hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,
                                const TileSweep *dev_sweeps, int n_sweeps, const TileGate *dev_gates,
-                               int slot0, int n_slots, double *partials, int n_blocks, hipStream_t s);
+                               int slot0, int n_slots, double *partials, int n_blocks, bool two_qubit,
+                               hipStream_t s);
 int adjoint_tile_qubits(int dtype);
 constexpr int kMaxAdjSlots = 128;
 

@@ -16,6 +16,8 @@
 
 #include "sv_internal.hpp"
 
+#include <type_traits>
+
 namespace sv {
 
 
@@ -129,120 +131,179 @@ __device__ __forceinline__ T gre(const TileGate &G, int i) {
     return reinterpret_cast<const T *>(G.m)[2 * i];
 }
 
-// x *= d with each component's own term taken last (see sweep_1q).
-template <typename T>
-__device__ __forceinline__ void cmul_inplace(cpx<T> &x, cpx<T> d) {
-    const T a = -d.im * x.im, b = d.im * x.re;
-    x.re = fma(d.re, x.re, a);
-    x.im = fma(d.re, x.im, b);
-}
+// ------------------------------------------------ in-place register updates
+// The amplitudes of a group stay in the registers they were loaded into for
+// the whole sweep.  Every update is inline assembly whose outputs are tied
+// to their inputs and which tests its own enable bit: bit J of the uniform
+// mask 'am' (a scalar test and branch inside the block).  A gate path is
+// then one straight run of such blocks, so the per-gate dispatch merges its
+// paths with the group in place and without copies.  Each output first
+// collects the terms that do not read its own input component and takes
+// that component in one final FMA.
+#define SV_SKIP_BEGIN "s_bitcmp1_b32 %[am], %[bit]\n\ts_cbranch_scc0 .Lsv_skip%=\n\t"
+#define SV_SKIP_END "\n.Lsv_skip%=:"
+#define SV_REG_ARITH(T, S)                                                                         \
+    /* x <- d x */                                                                                 \
+    template <int J>                                                                               \
+    __device__ __forceinline__ void rmul(cpx<T> &x, cpx<T> d, uint32_t am) {                       \
+        T t0, t1;                                                                                  \
+        asm volatile(SV_SKIP_BEGIN "v_mul_" S " %2, %5, %1\n\t"                                    \
+                                   "v_mul_" S " %3, %5, %0\n\t"                                    \
+                                   "v_fma_" S " %0, %4, %0, -%2\n\t"                               \
+                                   "v_fma_" S " %1, %4, %1, %3" SV_SKIP_END                        \
+                     : "+v"(x.re), "+v"(x.im), "=&v"(t0), "=&v"(t1)                                \
+                     : "v"(d.re), "v"(d.im), [am] "s"(am), [bit] "n"(J)                            \
+                     : "scc");                                                                     \
+    }                                                                                              \
+    /* (x0, x1) <- (g0 x0 + g1 x1, g2 x0 + g3 x1) */                                               \
+    template <int J>                                                                               \
+    __device__ __forceinline__ void rgen(cpx<T> &x0, cpx<T> &x1, const cpx<T> (&g)[4], uint32_t am) { \
+        T ar, ai, br, bi;                                                                          \
+        asm volatile(SV_SKIP_BEGIN "v_mul_" S " %4, -%9, %1\n\t"                                   \
+                                   "v_fma_" S " %4, -%11, %3, %4\n\t"                              \
+                                   "v_fma_" S " %4, %10, %2, %4\n\t"                               \
+                                   "v_mul_" S " %5, %9, %0\n\t"                                    \
+                                   "v_fma_" S " %5, %11, %2, %5\n\t"                               \
+                                   "v_fma_" S " %5, %10, %3, %5\n\t"                               \
+                                   "v_mul_" S " %6, -%15, %3\n\t"                                  \
+                                   "v_fma_" S " %6, -%13, %1, %6\n\t"                              \
+                                   "v_fma_" S " %6, %12, %0, %6\n\t"                               \
+                                   "v_mul_" S " %7, %15, %2\n\t"                                   \
+                                   "v_fma_" S " %7, %13, %0, %7\n\t"                               \
+                                   "v_fma_" S " %7, %12, %1, %7\n\t"                               \
+                                   "v_fma_" S " %0, %8, %0, %4\n\t"                                \
+                                   "v_fma_" S " %1, %8, %1, %5\n\t"                                \
+                                   "v_fma_" S " %2, %14, %2, %6\n\t"                               \
+                                   "v_fma_" S " %3, %14, %3, %7" SV_SKIP_END                       \
+                     : "+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),   \
+                       "=&v"(br), "=&v"(bi)                                                        \
+                     : "v"(g[0].re), "v"(g[0].im), "v"(g[1].re), "v"(g[1].im), "v"(g[2].re),       \
+                       "v"(g[2].im), "v"(g[3].re), "v"(g[3].im), [am] "s"(am), [bit] "n"(J)        \
+                     : "scc");                                                                     \
+    }                                                                                              \
+    /* (x0, x1) <- (r0 x0 + r1 x1, r2 x0 + r3 x1), r real */                                       \
+    template <int J>                                                                               \
+    __device__ __forceinline__ void rreal(cpx<T> &x0, cpx<T> &x1, const T (&r)[4], uint32_t am) {  \
+        T ar, ai, br, bi;                                                                          \
+        asm volatile(SV_SKIP_BEGIN "v_mul_" S " %4, %9, %2\n\t"                                    \
+                                   "v_mul_" S " %5, %9, %3\n\t"                                    \
+                                   "v_mul_" S " %6, %10, %0\n\t"                                   \
+                                   "v_mul_" S " %7, %10, %1\n\t"                                   \
+                                   "v_fma_" S " %0, %8, %0, %4\n\t"                                \
+                                   "v_fma_" S " %1, %8, %1, %5\n\t"                                \
+                                   "v_fma_" S " %2, %11, %2, %6\n\t"                               \
+                                   "v_fma_" S " %3, %11, %3, %7" SV_SKIP_END                       \
+                     : "+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),   \
+                       "=&v"(br), "=&v"(bi)                                                        \
+                     : "v"(r[0]), "v"(r[1]), "v"(r[2]), "v"(r[3]), [am] "s"(am), [bit] "n"(J)      \
+                     : "scc");                                                                     \
+    }                                                                                              \
+    /* x <- dr x + a (dr real) */                                                                  \
+    template <int J>                                                                               \
+    __device__ __forceinline__ void rfin(cpx<T> &x, T dr, cpx<T> a, uint32_t am) {                 \
+        asm volatile(SV_SKIP_BEGIN "v_fma_" S " %0, %2, %0, %3\n\t"                                \
+                                   "v_fma_" S " %1, %2, %1, %4" SV_SKIP_END                        \
+                     : "+v"(x.re), "+v"(x.im)                                                      \
+                     : "v"(dr), "v"(a.re), "v"(a.im), [am] "s"(am), [bit] "n"(J)                   \
+                     : "scc");                                                                     \
+    }
+SV_REG_ARITH(float, "f32")
+SV_REG_ARITH(double, "f64")
+#undef SV_REG_ARITH
 
-// Exchange two amplitudes held in registers without renaming registers
-// (a renamed set cannot share registers with the paths that leave the
-// group unchanged, and every gate then pays a copy of the whole group).
-__device__ __forceinline__ void swap_words(uint32_t &a, uint32_t &b) {
-    asm volatile("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+// Exchange two amplitudes held in registers, in place.
+template <int J>
+__device__ __forceinline__ void rswap(cpx<float> &a, cpx<float> &b, uint32_t am) {
+    asm volatile(SV_SKIP_BEGIN "v_swap_b32 %0, %2\n\t"
+                               "v_swap_b32 %1, %3" SV_SKIP_END
+                 : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+                 : [am] "s"(am), [bit] "n"(J)
+                 : "scc");
 }
-__device__ __forceinline__ void swap_f(float &a, float &b) {
-    uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
-    swap_words(x, y);
-    a = __builtin_bit_cast(float, x);
-    b = __builtin_bit_cast(float, y);
+template <int J>
+__device__ __forceinline__ void rswap(cpx<double> &a, cpx<double> &b, uint32_t am) {
+    double t0, t1;
+    asm volatile(SV_SKIP_BEGIN "v_mov_b64 %4, %0\n\t"
+                               "v_mov_b64 %5, %1\n\t"
+                               "v_mov_b64 %0, %2\n\t"
+                               "v_mov_b64 %1, %3\n\t"
+                               "v_mov_b64 %2, %4\n\t"
+                               "v_mov_b64 %3, %5" SV_SKIP_END
+                 : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im), "=&v"(t0), "=&v"(t1)
+                 : [am] "s"(am), [bit] "n"(J)
+                 : "scc");
 }
-__device__ __forceinline__ void swap_f(double &a, double &b) {
-    uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
-    uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32), yl = (uint32_t)y, yh = (uint32_t)(y >> 32);
-    swap_words(xl, yl);
-    swap_words(xh, yh);
-    a = __builtin_bit_cast(double, ((uint64_t)xh << 32) | xl);
-    b = __builtin_bit_cast(double, ((uint64_t)yh << 32) | yl);
-}
-template <typename T>
-__device__ __forceinline__ void swap_regs(cpx<T> &a, cpx<T> &b) {
-    swap_f(a.re, b.re);
-    swap_f(a.im, b.im);
-}
-// The local index of amplitude j of a group is gb | F[j]: gb holds the
-// group's own tile bits (per lane), F[j] the bits of register index j at the
-// sweep's positions (wave-uniform).  Every test of tile bits therefore splits
-// into one per-lane test of gb per gate and a uniform test of F[j] per
-// amplitude; gates without controls inside the tile compile the tests out.
-template <int W>
-struct GroupBits {
-    uint32_t gb;
-    uint32_t F[1 << W];
-    uint32_t fall; // all register position bits
-};
+#undef SV_SKIP_BEGIN
+#undef SV_SKIP_END
 
-// Per-lane part of a control test: the control bits outside the registers.
-template <int W>
-__device__ __forceinline__ bool lane_controls(const GroupBits<W> &g, uint32_t cin) {
-    const uint32_t cg = cin & ~g.fall;
-    return (g.gb & cg) == cg;
-}
-
-// Gate on register position P of a group of 2^W (pairs j, j | 2^P).
-template <typename T, int W, int P, bool CHECK>
-__device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], const GroupBits<W> &g, const TileGate &G,
-                                         int kind, uint32_t cin) {
-    constexpr int D = 1 << W;
-    const uint32_t cr = cin & g.fall;
-    if (CHECK && !lane_controls(g, cin)) return;
-    // Every output first collects the terms that do not read its own input
-    // component, then takes that component in one final FMA: the input dies
-    // at its last use and the result can stay in the same register.
-    if (kind == SK_GEN) {
-        const cpx<T> g0 = gmat<T>(G, 0), g1 = gmat<T>(G, 1), g2 = gmat<T>(G, 2), g3 = gmat<T>(G, 3);
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j & (1 << P)) continue;
-            if (CHECK && (g.F[j] & cr) != cr) continue;
-            const int c = j | (1 << P);
-            const cpx<T> x0 = v[j], x1 = v[c];
-            const T a_re = fma(g1.re, x1.re, fma(-g1.im, x1.im, -g0.im * x0.im));
-            const T a_im = fma(g1.re, x1.im, fma(g1.im, x1.re, g0.im * x0.re));
-            const T b_re = fma(g2.re, x0.re, fma(-g2.im, x0.im, -g3.im * x1.im));
-            const T b_im = fma(g2.re, x0.im, fma(g2.im, x0.re, g3.im * x1.re));
-            v[j] = cpx<T>{fma(g0.re, x0.re, a_re), fma(g0.re, x0.im, a_im)};
-            v[c] = cpx<T>{fma(g3.re, x1.re, b_re), fma(g3.re, x1.im, b_im)};
-        }
-    } else if (kind == SK_REAL) {
-        const T r0 = gre<T>(G, 0), r1 = gre<T>(G, 1), r2 = gre<T>(G, 2), r3 = gre<T>(G, 3);
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j & (1 << P)) continue;
-            if (CHECK && (g.F[j] & cr) != cr) continue;
-            const int c = j | (1 << P);
-            const cpx<T> x0 = v[j], x1 = v[c];
-            const T a_re = r1 * x1.re, a_im = r1 * x1.im, b_re = r2 * x0.re, b_im = r2 * x0.im;
-            v[j] = cpx<T>{fma(r0, x0.re, a_re), fma(r0, x0.im, a_im)};
-            v[c] = cpx<T>{fma(r3, x1.re, b_re), fma(r3, x1.im, b_im)};
-        }
-    } else { // SK_SWAP: exchanged in place, so no register is renamed
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j & (1 << P)) continue;
-            if (CHECK && (g.F[j] & cr) != cr) continue;
-            swap_regs(v[j], v[j | (1 << P)]);
-        }
+// Calls f(integral_constant<j>) for j = 0 .. N-1 with j in MASK.
+template <uint32_t MASK, int N, int J = 0, typename F>
+__device__ __forceinline__ void for_each_index(F &&f) {
+    if constexpr (J < N) {
+        if constexpr ((MASK >> J) & 1u) f(std::integral_constant<int, J>{});
+        for_each_index<MASK, N, J + 1>(f);
     }
 }
 
-template <typename T, int W, int P, int Q, bool CHECK>
-__device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], const GroupBits<W> &g, const TileGate &G,
-                                         uint32_t cin) {
+// Register indices of a group of 2^W whose bits in 'clear' are 0.
+template <int W>
+constexpr uint32_t index_set(uint32_t clear) {
+    uint32_t m = 0;
+    for (int j = 0; j < (1 << W); ++j)
+        if (!(j & clear)) m |= 1u << j;
+    return m;
+}
+
+// One-qubit gate on register position P (pairs j, j | 2^P).  A lane whose
+// group fails the per-lane controls applies the identity instead.
+template <typename T, int W, int P>
+__device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], bool ok, const TileGate &G, int kind,
+                                         uint32_t am) {
     constexpr int D = 1 << W;
-    const uint32_t cr = cin & g.fall;
-    if (CHECK && !lane_controls(g, cin)) return;
+    constexpr uint32_t PAIRS = index_set<W>(1u << P);
+    if (kind == SK_GEN) {
+        const cpx<T> one{T(1), T(0)}, zero{T(0), T(0)};
+        const cpx<T> g[4] = {ok ? gmat<T>(G, 0) : one, ok ? gmat<T>(G, 1) : zero, ok ? gmat<T>(G, 2) : zero,
+                             ok ? gmat<T>(G, 3) : one};
+        for_each_index<PAIRS, D>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            rgen<j>(v[j], v[j | (1 << P)], g, am);
+        });
+    } else if (kind == SK_REAL) {
+        const T r[4] = {ok ? gre<T>(G, 0) : T(1), ok ? gre<T>(G, 1) : T(0), ok ? gre<T>(G, 2) : T(0),
+                        ok ? gre<T>(G, 3) : T(1)};
+        for_each_index<PAIRS, D>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            rreal<j>(v[j], v[j | (1 << P)], r, am);
+        });
+    } else if (kind == SK_SWAP) { // never carries per-lane controls
+        for_each_index<PAIRS, D>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            rswap<j>(v[j], v[j | (1 << P)], am);
+        });
+    } else { // SK_DIAGR: amplitude j takes d1 if its bit P is set, else d0
+        const cpx<T> one{T(1), T(0)};
+        const cpx<T> d0 = ok ? gmat<T>(G, 0) : one, d1 = ok ? gmat<T>(G, 1) : one;
+        for_each_index<index_set<W>(0), D>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            rmul<j>(v[j], ((j >> P) & 1) ? d1 : d0, am);
+        });
+    }
+}
+
+// Two-qubit gate on register positions P < Q.  Lanes failing the per-lane
+// controls add nothing and keep their own terms (identity).
+template <typename T, int W, int P, int Q>
+__device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], bool ok, const TileGate &G, uint32_t am) {
+    constexpr uint32_t QUADS = index_set<W>((1u << P) | (1u << Q));
+    T dr[4];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        if (j & ((1 << P) | (1 << Q))) continue;
-        if (CHECK && (g.F[j] & cr) != cr) continue;
-        const int idx[4] = {j, j | (1 << P), j | (1 << Q), j | (1 << P) | (1 << Q)};
-        cpx<T> x[4], a[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = v[idx[q]];
-        // partial sums without each output's own component (see sweep_1q)
+    for (int r = 0; r < 4; ++r) dr[r] = ok ? gre<T>(G, 5 * r) : T(1);
+    for_each_index<QUADS, (1 << W)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int i1 = j | (1 << P), i2 = j | (1 << Q), i3 = j | (1 << P) | (1 << Q);
+        const cpx<T> x[4] = {v[j], v[i1], v[i2], v[i3]};
+        cpx<T> a[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const cpx<T> d = gmat<T>(G, 5 * r);
@@ -250,87 +311,123 @@ __device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], const GroupBits<W>
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if (c != r) acc = cfma(gmat<T>(G, 4 * r + c), x[c], acc);
-            a[r] = acc;
+            a[r] = ok ? acc : cpx<T>{T(0), T(0)};
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const T dr = gre<T>(G, 5 * r);
-            v[idx[r]] = cpx<T>{fma(dr, x[r].re, a[r].re), fma(dr, x[r].im, a[r].im)};
-        }
-    }
+        // every read of the old amplitudes happens before the first of them
+        // is overwritten in place
+        asm volatile("" : "+v"(a[0].re), "+v"(a[0].im), "+v"(a[1].re), "+v"(a[1].im), "+v"(a[2].re),
+                     "+v"(a[2].im), "+v"(a[3].re), "+v"(a[3].im));
+        rfin<j>(v[j], dr[0], a[0], am);
+        rfin<j>(v[i1], dr[1], a[1], am);
+        rfin<j>(v[i2], dr[2], a[2], am);
+        rfin<j>(v[i3], dr[3], a[3], am);
+    });
 }
 
-// diag(d0, d1) on tile bit b0.  On a register position the factor of each
-// amplitude is a uniform choice; on a group bit it is one choice per lane.
-template <typename T, int W, bool CHECK>
-__device__ __forceinline__ void sweep_diag(cpx<T> (&v)[1 << W], const GroupBits<W> &g, const TileGate &G,
-                                           uint32_t cin) {
-    constexpr int D = 1 << W;
+// diag(d0, d1) on tile bit b0 outside the registers: one factor per lane.
+template <typename T, int W>
+__device__ __forceinline__ void sweep_diag_lane(cpx<T> (&v)[1 << W], uint32_t gb, bool ok, const TileGate &G,
+                                                uint32_t am) {
+    const bool up = (gb >> G.b0) & 1u;
     const cpx<T> d0 = gmat<T>(G, 0), d1 = gmat<T>(G, 1);
-    const uint32_t bm = 1u << G.b0;
-    const uint32_t cr = cin & g.fall;
-    const bool d0_one = d0.re == T(1) && d0.im == T(0);
-    if (CHECK && !lane_controls(g, cin)) return;
-    if (bm & g.fall) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (CHECK && (g.F[j] & cr) != cr) continue;
-            const bool up = (g.F[j] & bm) != 0;
-            if (d0_one) {
-                if (up) cmul_inplace(v[j], d1);
+    const cpx<T> d = ok ? (up ? d1 : d0) : cpx<T>{T(1), T(0)};
+    for_each_index<index_set<W>(0), (1 << W)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        rmul<j>(v[j], d, am);
+    });
+}
+
+// Apply one record to a group held in registers; gb holds the group's own
+// tile bits, am the register indices to update (the record's amask, or 0
+// when its controls outside the tile fail).  Every branch of the dispatch
+// ends in the updates of one path (no empty path), so that the paths merge
+// with the group in its registers.  Two-qubit records are handled only by
+// the TWOQ instances: their partial sums, which read the old amplitudes
+// while others are rewritten, keep the compiler from holding the group in
+// place across the dispatch, so passes without them use kernels without
+// that path.
+template <typename T, int W, bool TWOQ>
+__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], uint32_t gb, const TileGate &G, uint32_t am) {
+    const int kind = G.kind;
+    const bool ok = (gb & G.lane) == G.lane;
+    am = __builtin_amdgcn_readfirstlane(am);
+    if (kind == SK_DIAG) {
+        sweep_diag_lane<T, W>(v, gb, ok, G, am);
+    } else if (TWOQ && W >= 2 && kind == SK_2Q) {
+        if constexpr (TWOQ && W >= 2) {
+            const int pq = G.b0 * 4 + G.b1;
+            if constexpr (W == 2) {
+                sweep_2q<T, W, 0, 1>(v, ok, G, am);
+            } else if constexpr (W == 3) {
+                if (pq == 1) sweep_2q<T, W, 0, 1>(v, ok, G, am);
+                else if (pq == 2) sweep_2q<T, W, 0, 2>(v, ok, G, am);
+                else sweep_2q<T, W, 1, 2>(v, ok, G, am);
             } else {
-                cmul_inplace(v[j], up ? d1 : d0);
+                if (pq == 1) sweep_2q<T, W, 0, 1>(v, ok, G, am);
+                else if (pq == 2) sweep_2q<T, W, 0, 2>(v, ok, G, am);
+                else if (pq == 6) sweep_2q<T, W, 1, 2>(v, ok, G, am);
+                else if (pq == 3) sweep_2q<T, W, 0, 3>(v, ok, G, am);
+                else if (pq == 7) sweep_2q<T, W, 1, 3>(v, ok, G, am);
+                else sweep_2q<T, W, 2, 3>(v, ok, G, am);
             }
         }
     } else {
-        const bool up = (g.gb & bm) != 0;
-        if (d0_one && !up) return; // phase gate: only amplitudes with the bit set change
-        const cpx<T> d{up ? d1.re : d0.re, up ? d1.im : d0.im}; // component-wise select
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (CHECK && (g.F[j] & cr) != cr) continue;
-            cmul_inplace(v[j], d);
+        const int p = G.b0;
+        if constexpr (W == 1) {
+            sweep_1q<T, W, 0>(v, ok, G, kind, am);
+        } else if constexpr (W == 2) {
+            if (p == 0) sweep_1q<T, W, 0>(v, ok, G, kind, am);
+            else sweep_1q<T, W, 1>(v, ok, G, kind, am);
+        } else if constexpr (W == 3) {
+            if (p == 0) sweep_1q<T, W, 0>(v, ok, G, kind, am);
+            else if (p == 1) sweep_1q<T, W, 1>(v, ok, G, kind, am);
+            else sweep_1q<T, W, 2>(v, ok, G, kind, am);
+        } else {
+            if (p == 0) sweep_1q<T, W, 0>(v, ok, G, kind, am);
+            else if (p == 1) sweep_1q<T, W, 1>(v, ok, G, kind, am);
+            else if (p == 2) sweep_1q<T, W, 2>(v, ok, G, kind, am);
+            else sweep_1q<T, W, 3>(v, ok, G, kind, am);
         }
     }
 }
 
-template <typename T, int W, bool CHECK>
-__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], const GroupBits<W> &li, const TileGate &G) {
-    const int kind = G.kind;
-    const uint32_t cin = G.cin;
-    if (kind == SK_DIAG) {
-        sweep_diag<T, W, CHECK>(v, li, G, cin);
-        return;
+// Enable mask of a record for the tile at global index base.
+__device__ __forceinline__ uint32_t record_mask(const TileGate &G, uint64_t base) {
+    return (base & G.cout) == G.cout ? G.amask : 0u;
+}
+
+// Tile bits of the sweep's register positions: gb (the group's own bits,
+// per lane) spreads group index g around them.
+template <int W>
+__device__ __forceinline__ uint32_t group_bits(const TileSweep &S, uint32_t g) {
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        const uint32_t low = (1u << S.qpos[b]) - 1u;
+        g = (g & low) | ((g & ~low) << 1);
     }
-    if (kind == SK_2Q) {
-        if constexpr (W >= 2) {
-            const int pq = G.b0 * 4 + G.b1;
-            if (pq == 1) { sweep_2q<T, W, 0, 1, CHECK>(v, li, G, cin); return; }
-            if constexpr (W >= 3) {
-                if (pq == 2) { sweep_2q<T, W, 0, 2, CHECK>(v, li, G, cin); return; }
-                if (pq == 6) { sweep_2q<T, W, 1, 2, CHECK>(v, li, G, cin); return; }
-            }
-            if constexpr (W >= 4) {
-                if (pq == 3) { sweep_2q<T, W, 0, 3, CHECK>(v, li, G, cin); return; }
-                if (pq == 7) { sweep_2q<T, W, 1, 3, CHECK>(v, li, G, cin); return; }
-                if (pq == 11) { sweep_2q<T, W, 2, 3, CHECK>(v, li, G, cin); return; }
-            }
-        }
-        return;
+    return g;
+}
+
+// LDS offsets (swizzled) of the register indices' bits, uniform per sweep.
+template <typename T, int W>
+__device__ __forceinline__ void register_offsets(const TileSweep &S, uint32_t (&PF)[1 << W]) {
+#pragma unroll
+    for (int j = 0; j < (1 << W); ++j) {
+        uint32_t f = 0;
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+            if ((j >> b) & 1) f |= 1u << S.qpos[b];
+        PF[j] = lds_phys<T>(f);
     }
-    const int p = G.b0;
-    if (p == 0) { sweep_1q<T, W, 0, CHECK>(v, li, G, kind, cin); return; }
-    if constexpr (W >= 2) if (p == 1) { sweep_1q<T, W, 1, CHECK>(v, li, G, kind, cin); return; }
-    if constexpr (W >= 3) if (p == 2) { sweep_1q<T, W, 2, CHECK>(v, li, G, kind, cin); return; }
-    if constexpr (W >= 4) if (p == 3) { sweep_1q<T, W, 3, CHECK>(v, li, G, kind, cin); return; }
 }
 
 // Apply the sweeps of one pass to the tile in LDS.  'base' is the global
 // index of the tile's local amplitude 0 (for controls outside the tile).
 // Caller synchronises before (tile loaded); every sweep ends with a barrier.
-// The LDS swizzle is linear over XOR and gb, F[j] have disjoint bits, so the
-// address of amplitude j is lds_phys(gb) ^ lds_phys(F[j]).
-template <typename T, int W>
+// The LDS swizzle is linear over XOR and a group's bits are disjoint from
+// the register bits, so amplitude j of the group sits at
+// lds_phys(gb) ^ lds_phys(register bits of j).
+template <typename T, int W, bool TWOQ>
 __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSweep *__restrict__ sweeps,
                                 int n_sweeps, const TileGate *__restrict__ gates) {
     constexpr int D = 1 << W;
@@ -339,41 +436,24 @@ __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSwe
     for (int si = 0; si < n_sweeps; ++si) {
         const TileSweep &S = sweeps[si];
         const int ng = S.n_gates;
-        uint32_t F[D], PF[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            uint32_t f = 0;
-#pragma unroll
-            for (int b = 0; b < W; ++b)
-                if ((j >> b) & 1) f |= 1u << S.qpos[b];
-            F[j] = f;
-            PF[j] = lds_phys<T>(f);
-        }
+        uint32_t PF[D];
+        register_offsets<T, W>(S, PF);
         for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
-            uint32_t gb = g;
-#pragma unroll
-            for (int b = 0; b < W; ++b) {
-                const uint32_t low = (1u << S.qpos[b]) - 1u;
-                gb = (gb & low) | ((gb & ~low) << 1);
-            }
+            const uint32_t gb = group_bits<W>(S, g);
             const uint32_t pg = lds_phys<T>(gb);
             cpx<T> v[D];
-            GroupBits<W> li;
-            li.gb = gb;
-            li.fall = F[D - 1];
+            uint32_t addr[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                li.F[j] = F[j];
-                v[j] = lds[pg ^ PF[j]];
+                addr[j] = pg ^ PF[j];
+                v[j] = lds[addr[j]];
             }
             for (int gi = 0; gi < ng; ++gi) {
                 const TileGate &G = gates[goff + gi];
-                if ((base & G.cout) != G.cout) continue; // uniform
-                if (G.cin == 0) sweep_gate_t<T, W, false>(v, li, G);
-                else sweep_gate_t<T, W, true>(v, li, G);
+                sweep_gate_t<T, W, TWOQ>(v, gb, G, record_mask(G, base));
             }
 #pragma unroll
-            for (int j = 0; j < D; ++j) lds[pg ^ PF[j]] = v[j];
+            for (int j = 0; j < D; ++j) lds[addr[j]] = v[j];
         }
         goff += ng;
         __syncthreads();
