@@ -215,8 +215,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                         const double c = wave_sum_d(mine);
                         if ((threadIdx.x & 63) == 0) atomicAdd(&slot_acc[G.b1], c);
                     } else {
-                        sweep_gate_t<T, W, TWOQ>(v, gb, G, record_mask(G, base));
-                        sweep_gate_t<T, W, TWOQ>(w, gb, G, record_mask(G, base));
+                        sweep_gate_t<T, W, TWOQ>(v, gb, G, base);
+                        sweep_gate_t<T, W, TWOQ>(w, gb, G, base);
                     }
                 }
                 if (act) {

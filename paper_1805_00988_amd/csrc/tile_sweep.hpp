@@ -16,6 +16,7 @@
 
 #include "sv_internal.hpp"
 
+#include <cstddef>
 #include <type_traits>
 
 namespace sv {
@@ -134,105 +135,112 @@ __device__ __forceinline__ T gre(const TileGate &G, int i) {
 // ------------------------------------------------ in-place register updates
 // The amplitudes of a group stay in the registers they were loaded into for
 // the whole sweep.  Every update is inline assembly whose outputs are tied
-// to their inputs and which tests its own enable bit: bit J of the uniform
-// mask 'am' (a scalar test and branch inside the block).  A gate path is
-// then one straight run of such blocks, so the per-gate dispatch merges its
-// paths with the group in place and without copies.  Each output first
-// collects the terms that do not read its own input component and takes
-// that component in one final FMA.
+// to their inputs.  With TEST it checks its own enable bit, bit J of the
+// uniform mask 'am' (a scalar test and branch inside the block); without,
+// it runs unconditionally.  A gate path is then one straight run of such
+// blocks, so the per-gate dispatch merges its paths with the group in place
+// and without copies.  Each output first collects the terms that do not
+// read its own input component and takes that component in one final FMA.
 #define SV_SKIP_BEGIN "s_bitcmp1_b32 %[am], %[bit]\n\ts_cbranch_scc0 .Lsv_skip%=\n\t"
 #define SV_SKIP_END "\n.Lsv_skip%=:"
+#define SV_ASM(TEXT, OUTS, INS)                                                                    \
+    if constexpr (TEST)                                                                            \
+        asm volatile(SV_SKIP_BEGIN TEXT SV_SKIP_END : OUTS : INS, [am] "s"(am), [bit] "n"(J) : "scc"); \
+    else                                                                                           \
+        asm volatile(TEXT : OUTS : INS)
+#define SV_ASM_NOIN(TEXT, OUTS)                                                                    \
+    if constexpr (TEST)                                                                            \
+        asm volatile(SV_SKIP_BEGIN TEXT SV_SKIP_END : OUTS : [am] "s"(am), [bit] "n"(J) : "scc");  \
+    else                                                                                           \
+        asm volatile(TEXT : OUTS)
 #define SV_REG_ARITH(T, S)                                                                         \
     /* x <- d x */                                                                                 \
-    template <int J>                                                                               \
+    template <int J, bool TEST>                                                                    \
     __device__ __forceinline__ void rmul(cpx<T> &x, cpx<T> d, uint32_t am) {                       \
         T t0, t1;                                                                                  \
-        asm volatile(SV_SKIP_BEGIN "v_mul_" S " %2, %5, %1\n\t"                                    \
-                                   "v_mul_" S " %3, %5, %0\n\t"                                    \
-                                   "v_fma_" S " %0, %4, %0, -%2\n\t"                               \
-                                   "v_fma_" S " %1, %4, %1, %3" SV_SKIP_END                        \
-                     : "+v"(x.re), "+v"(x.im), "=&v"(t0), "=&v"(t1)                                \
-                     : "v"(d.re), "v"(d.im), [am] "s"(am), [bit] "n"(J)                            \
-                     : "scc");                                                                     \
+        SV_ASM("v_mul_" S " %2, %5, %1\n\t"                                                        \
+               "v_mul_" S " %3, %5, %0\n\t"                                                        \
+               "v_fma_" S " %0, %4, %0, -%2\n\t"                                                   \
+               "v_fma_" S " %1, %4, %1, %3",                                                       \
+               SV_OUTS("+v"(x.re), "+v"(x.im), "=&v"(t0), "=&v"(t1)),                               \
+               SV_INS("v"(d.re), "v"(d.im)));                                                      \
     }                                                                                              \
     /* (x0, x1) <- (g0 x0 + g1 x1, g2 x0 + g3 x1) */                                               \
-    template <int J>                                                                               \
+    template <int J, bool TEST>                                                                    \
     __device__ __forceinline__ void rgen(cpx<T> &x0, cpx<T> &x1, const cpx<T> (&g)[4], uint32_t am) { \
         T ar, ai, br, bi;                                                                          \
-        asm volatile(SV_SKIP_BEGIN "v_mul_" S " %4, -%9, %1\n\t"                                   \
-                                   "v_fma_" S " %4, -%11, %3, %4\n\t"                              \
-                                   "v_fma_" S " %4, %10, %2, %4\n\t"                               \
-                                   "v_mul_" S " %5, %9, %0\n\t"                                    \
-                                   "v_fma_" S " %5, %11, %2, %5\n\t"                               \
-                                   "v_fma_" S " %5, %10, %3, %5\n\t"                               \
-                                   "v_mul_" S " %6, -%15, %3\n\t"                                  \
-                                   "v_fma_" S " %6, -%13, %1, %6\n\t"                              \
-                                   "v_fma_" S " %6, %12, %0, %6\n\t"                               \
-                                   "v_mul_" S " %7, %15, %2\n\t"                                   \
-                                   "v_fma_" S " %7, %13, %0, %7\n\t"                               \
-                                   "v_fma_" S " %7, %12, %1, %7\n\t"                               \
-                                   "v_fma_" S " %0, %8, %0, %4\n\t"                                \
-                                   "v_fma_" S " %1, %8, %1, %5\n\t"                                \
-                                   "v_fma_" S " %2, %14, %2, %6\n\t"                               \
-                                   "v_fma_" S " %3, %14, %3, %7" SV_SKIP_END                       \
-                     : "+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),   \
-                       "=&v"(br), "=&v"(bi)                                                        \
-                     : "v"(g[0].re), "v"(g[0].im), "v"(g[1].re), "v"(g[1].im), "v"(g[2].re),       \
-                       "v"(g[2].im), "v"(g[3].re), "v"(g[3].im), [am] "s"(am), [bit] "n"(J)        \
-                     : "scc");                                                                     \
+        SV_ASM("v_mul_" S " %4, -%9, %1\n\t"                                                       \
+               "v_fma_" S " %4, -%11, %3, %4\n\t"                                                  \
+               "v_fma_" S " %4, %10, %2, %4\n\t"                                                   \
+               "v_mul_" S " %5, %9, %0\n\t"                                                        \
+               "v_fma_" S " %5, %11, %2, %5\n\t"                                                   \
+               "v_fma_" S " %5, %10, %3, %5\n\t"                                                   \
+               "v_mul_" S " %6, -%15, %3\n\t"                                                      \
+               "v_fma_" S " %6, -%13, %1, %6\n\t"                                                  \
+               "v_fma_" S " %6, %12, %0, %6\n\t"                                                   \
+               "v_mul_" S " %7, %15, %2\n\t"                                                       \
+               "v_fma_" S " %7, %13, %0, %7\n\t"                                                   \
+               "v_fma_" S " %7, %12, %1, %7\n\t"                                                   \
+               "v_fma_" S " %0, %8, %0, %4\n\t"                                                    \
+               "v_fma_" S " %1, %8, %1, %5\n\t"                                                    \
+               "v_fma_" S " %2, %14, %2, %6\n\t"                                                   \
+               "v_fma_" S " %3, %14, %3, %7",                                                      \
+               SV_OUTS("+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),    \
+                       "=&v"(br), "=&v"(bi)),                                                      \
+               SV_INS("v"(g[0].re), "v"(g[0].im), "v"(g[1].re), "v"(g[1].im), "v"(g[2].re),        \
+                      "v"(g[2].im), "v"(g[3].re), "v"(g[3].im)));                                  \
     }                                                                                              \
     /* (x0, x1) <- (r0 x0 + r1 x1, r2 x0 + r3 x1), r real */                                       \
-    template <int J>                                                                               \
+    template <int J, bool TEST>                                                                    \
     __device__ __forceinline__ void rreal(cpx<T> &x0, cpx<T> &x1, const T (&r)[4], uint32_t am) {  \
         T ar, ai, br, bi;                                                                          \
-        asm volatile(SV_SKIP_BEGIN "v_mul_" S " %4, %9, %2\n\t"                                    \
-                                   "v_mul_" S " %5, %9, %3\n\t"                                    \
-                                   "v_mul_" S " %6, %10, %0\n\t"                                   \
-                                   "v_mul_" S " %7, %10, %1\n\t"                                   \
-                                   "v_fma_" S " %0, %8, %0, %4\n\t"                                \
-                                   "v_fma_" S " %1, %8, %1, %5\n\t"                                \
-                                   "v_fma_" S " %2, %11, %2, %6\n\t"                               \
-                                   "v_fma_" S " %3, %11, %3, %7" SV_SKIP_END                       \
-                     : "+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),   \
-                       "=&v"(br), "=&v"(bi)                                                        \
-                     : "v"(r[0]), "v"(r[1]), "v"(r[2]), "v"(r[3]), [am] "s"(am), [bit] "n"(J)      \
-                     : "scc");                                                                     \
+        SV_ASM("v_mul_" S " %4, %9, %2\n\t"                                                        \
+               "v_mul_" S " %5, %9, %3\n\t"                                                        \
+               "v_mul_" S " %6, %10, %0\n\t"                                                       \
+               "v_mul_" S " %7, %10, %1\n\t"                                                       \
+               "v_fma_" S " %0, %8, %0, %4\n\t"                                                    \
+               "v_fma_" S " %1, %8, %1, %5\n\t"                                                    \
+               "v_fma_" S " %2, %11, %2, %6\n\t"                                                   \
+               "v_fma_" S " %3, %11, %3, %7",                                                      \
+               SV_OUTS("+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),    \
+                       "=&v"(br), "=&v"(bi)),                                                      \
+               SV_INS("v"(r[0]), "v"(r[1]), "v"(r[2]), "v"(r[3])));                                \
     }                                                                                              \
     /* x <- dr x + a (dr real) */                                                                  \
-    template <int J>                                                                               \
+    template <int J, bool TEST>                                                                    \
     __device__ __forceinline__ void rfin(cpx<T> &x, T dr, cpx<T> a, uint32_t am) {                 \
-        asm volatile(SV_SKIP_BEGIN "v_fma_" S " %0, %2, %0, %3\n\t"                                \
-                                   "v_fma_" S " %1, %2, %1, %4" SV_SKIP_END                        \
-                     : "+v"(x.re), "+v"(x.im)                                                      \
-                     : "v"(dr), "v"(a.re), "v"(a.im), [am] "s"(am), [bit] "n"(J)                   \
-                     : "scc");                                                                     \
+        SV_ASM("v_fma_" S " %0, %2, %0, %3\n\t"                                                    \
+               "v_fma_" S " %1, %2, %1, %4",                                                       \
+               SV_OUTS("+v"(x.re), "+v"(x.im)), SV_INS("v"(dr), "v"(a.re), "v"(a.im)));            \
     }
+#define SV_OUTS(...) __VA_ARGS__
+#define SV_INS(...) __VA_ARGS__
 SV_REG_ARITH(float, "f32")
 SV_REG_ARITH(double, "f64")
 #undef SV_REG_ARITH
 
 // Exchange two amplitudes held in registers, in place.
-template <int J>
+template <int J, bool TEST>
 __device__ __forceinline__ void rswap(cpx<float> &a, cpx<float> &b, uint32_t am) {
-    asm volatile(SV_SKIP_BEGIN "v_swap_b32 %0, %2\n\t"
-                               "v_swap_b32 %1, %3" SV_SKIP_END
-                 : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
-                 : [am] "s"(am), [bit] "n"(J)
-                 : "scc");
+    SV_ASM_NOIN("v_swap_b32 %0, %2\n\t"
+                "v_swap_b32 %1, %3",
+                SV_OUTS("+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)));
 }
-template <int J>
+template <int J, bool TEST>
 __device__ __forceinline__ void rswap(cpx<double> &a, cpx<double> &b, uint32_t am) {
     double t0, t1;
-    asm volatile(SV_SKIP_BEGIN "v_mov_b64 %4, %0\n\t"
-                               "v_mov_b64 %5, %1\n\t"
-                               "v_mov_b64 %0, %2\n\t"
-                               "v_mov_b64 %1, %3\n\t"
-                               "v_mov_b64 %2, %4\n\t"
-                               "v_mov_b64 %3, %5" SV_SKIP_END
-                 : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im), "=&v"(t0), "=&v"(t1)
-                 : [am] "s"(am), [bit] "n"(J)
-                 : "scc");
+    SV_ASM_NOIN("v_mov_b64 %4, %0\n\t"
+                "v_mov_b64 %5, %1\n\t"
+                "v_mov_b64 %0, %2\n\t"
+                "v_mov_b64 %1, %3\n\t"
+                "v_mov_b64 %2, %4\n\t"
+                "v_mov_b64 %3, %5",
+                SV_OUTS("+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im), "=&v"(t0), "=&v"(t1)));
 }
+#undef SV_OUTS
+#undef SV_INS
+#undef SV_ASM
+#undef SV_ASM_NOIN
 #undef SV_SKIP_BEGIN
 #undef SV_SKIP_END
 
@@ -245,6 +253,19 @@ __device__ __forceinline__ void for_each_index(F &&f) {
     }
 }
 
+// f over the register indices of FULL (compile-time) that am enables: as
+// unconditional updates when am is all of FULL (the common case: no control
+// on a register position), else each behind its own enable test.  f takes
+// the index and the TEST flag as integral constants.
+template <uint32_t FULL, int N, typename F>
+__device__ __forceinline__ void over_mask(uint32_t am, F &&f) {
+    if (am == FULL) {
+        for_each_index<FULL, N>([&](auto jc) { f(jc, std::false_type{}); });
+    } else {
+        for_each_index<FULL, N>([&](auto jc) { f(jc, std::true_type{}); });
+    }
+}
+
 // Register indices of a group of 2^W whose bits in 'clear' are 0.
 template <int W>
 constexpr uint32_t index_set(uint32_t clear) {
@@ -254,40 +275,51 @@ constexpr uint32_t index_set(uint32_t clear) {
     return m;
 }
 
+// The leading 96 bytes of a record: the header and the matrix entries a
+// one-qubit record uses, read with one batch of scalar loads per gate.
+struct GateHot {
+    int32_t kind, b0, b1;
+    uint32_t lane, amask, pad;
+    uint64_t cout;
+    uint32_t m[16];
+};
+static_assert(offsetof(TileGate, m) == offsetof(GateHot, m), "record layout");
+template <typename T>
+__device__ __forceinline__ cpx<T> hmat(const GateHot &h, int i) {
+    const T *m = reinterpret_cast<const T *>(h.m);
+    return cpx<T>{m[2 * i], m[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ T hre(const GateHot &h, int i) {
+    return reinterpret_cast<const T *>(h.m)[2 * i];
+}
+
+#define SV_J constexpr int j = decltype(jc)::value; constexpr bool t = decltype(tc)::value
 // One-qubit gate on register position P (pairs j, j | 2^P).  A lane whose
 // group fails the per-lane controls applies the identity instead.
 template <typename T, int W, int P>
-__device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], bool ok, const TileGate &G, int kind,
-                                         uint32_t am) {
+__device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], bool ok, const GateHot &h, uint32_t am) {
     constexpr int D = 1 << W;
     constexpr uint32_t PAIRS = index_set<W>(1u << P);
+    const int kind = h.kind;
     if (kind == SK_GEN) {
         const cpx<T> one{T(1), T(0)}, zero{T(0), T(0)};
-        const cpx<T> g[4] = {ok ? gmat<T>(G, 0) : one, ok ? gmat<T>(G, 1) : zero, ok ? gmat<T>(G, 2) : zero,
-                             ok ? gmat<T>(G, 3) : one};
-        for_each_index<PAIRS, D>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            rgen<j>(v[j], v[j | (1 << P)], g, am);
-        });
+        const cpx<T> g[4] = {ok ? hmat<T>(h, 0) : one, ok ? hmat<T>(h, 1) : zero, ok ? hmat<T>(h, 2) : zero,
+                             ok ? hmat<T>(h, 3) : one};
+        over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rgen<j, t>(v[j], v[j | (1 << P)], g, am); });
     } else if (kind == SK_REAL) {
-        const T r[4] = {ok ? gre<T>(G, 0) : T(1), ok ? gre<T>(G, 1) : T(0), ok ? gre<T>(G, 2) : T(0),
-                        ok ? gre<T>(G, 3) : T(1)};
-        for_each_index<PAIRS, D>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            rreal<j>(v[j], v[j | (1 << P)], r, am);
-        });
+        const T r[4] = {ok ? hre<T>(h, 0) : T(1), ok ? hre<T>(h, 1) : T(0), ok ? hre<T>(h, 2) : T(0),
+                        ok ? hre<T>(h, 3) : T(1)};
+        over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rreal<j, t>(v[j], v[j | (1 << P)], r, am); });
     } else if (kind == SK_SWAP) { // never carries per-lane controls
-        for_each_index<PAIRS, D>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            rswap<j>(v[j], v[j | (1 << P)], am);
-        });
+        over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rswap<j, t>(v[j], v[j | (1 << P)], am); });
     } else { // SK_DIAGR: amplitude j takes d1 if its bit P is set, else d0
         const cpx<T> one{T(1), T(0)};
-        const cpx<T> d0 = ok ? gmat<T>(G, 0) : one, d1 = ok ? gmat<T>(G, 1) : one;
-        for_each_index<index_set<W>(0), D>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            rmul<j>(v[j], ((j >> P) & 1) ? d1 : d0, am);
-        });
+        const cpx<T> d0 = ok ? hmat<T>(h, 0) : one, d1 = ok ? hmat<T>(h, 1) : one;
+        constexpr uint32_t UP = index_set<W>(0) & ~PAIRS;
+        auto f = [&](auto jc, auto tc) { SV_J; rmul<j, t>(v[j], ((j >> P) & 1) ? d1 : d0, am); };
+        if (am == UP) for_each_index<UP, D>([&](auto jc) { f(jc, std::false_type{}); }); // phase gate
+        else over_mask<index_set<W>(0), D>(am, f);
     }
 }
 
@@ -317,45 +349,44 @@ __device__ __forceinline__ void sweep_2q(cpx<T> (&v)[1 << W], bool ok, const Til
         // is overwritten in place
         asm volatile("" : "+v"(a[0].re), "+v"(a[0].im), "+v"(a[1].re), "+v"(a[1].im), "+v"(a[2].re),
                      "+v"(a[2].im), "+v"(a[3].re), "+v"(a[3].im));
-        rfin<j>(v[j], dr[0], a[0], am);
-        rfin<j>(v[i1], dr[1], a[1], am);
-        rfin<j>(v[i2], dr[2], a[2], am);
-        rfin<j>(v[i3], dr[3], a[3], am);
+        rfin<j, true>(v[j], dr[0], a[0], am);
+        rfin<j, true>(v[i1], dr[1], a[1], am);
+        rfin<j, true>(v[i2], dr[2], a[2], am);
+        rfin<j, true>(v[i3], dr[3], a[3], am);
     });
 }
 
 // diag(d0, d1) on tile bit b0 outside the registers: one factor per lane.
 template <typename T, int W>
-__device__ __forceinline__ void sweep_diag_lane(cpx<T> (&v)[1 << W], uint32_t gb, bool ok, const TileGate &G,
+__device__ __forceinline__ void sweep_diag_lane(cpx<T> (&v)[1 << W], uint32_t gb, bool ok, const GateHot &h,
                                                 uint32_t am) {
-    const bool up = (gb >> G.b0) & 1u;
-    const cpx<T> d0 = gmat<T>(G, 0), d1 = gmat<T>(G, 1);
+    const bool up = (gb >> h.b0) & 1u;
+    const cpx<T> d0 = hmat<T>(h, 0), d1 = hmat<T>(h, 1);
     const cpx<T> d = ok ? (up ? d1 : d0) : cpx<T>{T(1), T(0)};
-    for_each_index<index_set<W>(0), (1 << W)>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        rmul<j>(v[j], d, am);
-    });
+    over_mask<index_set<W>(0), (1 << W)>(am, [&](auto jc, auto tc) { SV_J; rmul<j, t>(v[j], d, am); });
 }
+#undef SV_J
 
 // Apply one record to a group held in registers; gb holds the group's own
-// tile bits, am the register indices to update (the record's amask, or 0
-// when its controls outside the tile fail).  Every branch of the dispatch
-// ends in the updates of one path (no empty path), so that the paths merge
-// with the group in its registers.  Two-qubit records are handled only by
-// the TWOQ instances: their partial sums, which read the old amplitudes
-// while others are rewritten, keep the compiler from holding the group in
-// place across the dispatch, so passes without them use kernels without
-// that path.
+// tile bits, base is the global index of the tile's amplitude 0 (the
+// record's controls outside the tile hold for the whole tile or not at all:
+// then its enable mask is 0).  Every branch of the dispatch ends in the
+// updates of one path (no empty path), so that the paths merge with the
+// group in its registers.  Two-qubit records are handled only by the TWOQ
+// instances: their partial sums, which read the old amplitudes while others
+// are rewritten, keep the compiler from holding the group in place across
+// the dispatch, so passes without them use kernels without that path.
 template <typename T, int W, bool TWOQ>
-__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], uint32_t gb, const TileGate &G, uint32_t am) {
-    const int kind = G.kind;
-    const bool ok = (gb & G.lane) == G.lane;
-    am = __builtin_amdgcn_readfirstlane(am);
+__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], uint32_t gb, const TileGate &G, uint64_t base) {
+    const GateHot h = *reinterpret_cast<const GateHot *>(&G);
+    const int kind = h.kind;
+    const bool ok = (gb & h.lane) == h.lane;
+    const uint32_t am = __builtin_amdgcn_readfirstlane((base & h.cout) == h.cout ? h.amask : 0u);
     if (kind == SK_DIAG) {
-        sweep_diag_lane<T, W>(v, gb, ok, G, am);
+        sweep_diag_lane<T, W>(v, gb, ok, h, am);
     } else if (TWOQ && W >= 2 && kind == SK_2Q) {
         if constexpr (TWOQ && W >= 2) {
-            const int pq = G.b0 * 4 + G.b1;
+            const int pq = h.b0 * 4 + h.b1;
             if constexpr (W == 2) {
                 sweep_2q<T, W, 0, 1>(v, ok, G, am);
             } else if constexpr (W == 3) {
@@ -372,28 +403,23 @@ __device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], uint32_t gb, c
             }
         }
     } else {
-        const int p = G.b0;
+        const int p = h.b0;
         if constexpr (W == 1) {
-            sweep_1q<T, W, 0>(v, ok, G, kind, am);
+            sweep_1q<T, W, 0>(v, ok, h, am);
         } else if constexpr (W == 2) {
-            if (p == 0) sweep_1q<T, W, 0>(v, ok, G, kind, am);
-            else sweep_1q<T, W, 1>(v, ok, G, kind, am);
+            if (p == 0) sweep_1q<T, W, 0>(v, ok, h, am);
+            else sweep_1q<T, W, 1>(v, ok, h, am);
         } else if constexpr (W == 3) {
-            if (p == 0) sweep_1q<T, W, 0>(v, ok, G, kind, am);
-            else if (p == 1) sweep_1q<T, W, 1>(v, ok, G, kind, am);
-            else sweep_1q<T, W, 2>(v, ok, G, kind, am);
+            if (p == 0) sweep_1q<T, W, 0>(v, ok, h, am);
+            else if (p == 1) sweep_1q<T, W, 1>(v, ok, h, am);
+            else sweep_1q<T, W, 2>(v, ok, h, am);
         } else {
-            if (p == 0) sweep_1q<T, W, 0>(v, ok, G, kind, am);
-            else if (p == 1) sweep_1q<T, W, 1>(v, ok, G, kind, am);
-            else if (p == 2) sweep_1q<T, W, 2>(v, ok, G, kind, am);
-            else sweep_1q<T, W, 3>(v, ok, G, kind, am);
+            if (p == 0) sweep_1q<T, W, 0>(v, ok, h, am);
+            else if (p == 1) sweep_1q<T, W, 1>(v, ok, h, am);
+            else if (p == 2) sweep_1q<T, W, 2>(v, ok, h, am);
+            else sweep_1q<T, W, 3>(v, ok, h, am);
         }
     }
-}
-
-// Enable mask of a record for the tile at global index base.
-__device__ __forceinline__ uint32_t record_mask(const TileGate &G, uint64_t base) {
-    return (base & G.cout) == G.cout ? G.amask : 0u;
 }
 
 // Tile bits of the sweep's register positions: gb (the group's own bits,
@@ -450,7 +476,7 @@ __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSwe
             }
             for (int gi = 0; gi < ng; ++gi) {
                 const TileGate &G = gates[goff + gi];
-                sweep_gate_t<T, W, TWOQ>(v, gb, G, record_mask(G, base));
+                sweep_gate_t<T, W, TWOQ>(v, gb, G, base);
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) lds[addr[j]] = v[j];
