@@ -368,38 +368,108 @@ __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t bas
     return g;
 }
 
+// The pass's sweeps over one tile.  The first sweep reads its groups
+// straight from the state and the last writes them straight back, so the
+// tile crosses LDS only between sweeps (a pass of one sweep never touches
+// it); each sweep ends with a barrier, which also keeps the next tile's
+// first LDS writes behind this tile's last LDS reads.
+template <typename T, int W, bool TWOQ>
+__device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const TileSpec &sp, uint64_t base,
+                                 int m, const TileSweep *__restrict__ sweeps, int n_sweeps,
+                                 const TileGate *__restrict__ gates, uint32_t direct) {
+    constexpr int D = 1 << W;
+    const uint32_t n_groups = (1u << m) >> W;
+    using V = typename Vec<T>::type;
+    if (!(direct & kDirectFirst)) {
+        tile_load<T, kTileThreads, 8>(reinterpret_cast<const V *>(state), lds, sp, base, 1u << m);
+        __syncthreads();
+    }
+    int goff = 0;
+    for (int si = 0; si < n_sweeps; ++si) {
+        const TileSweep &S = sweeps[si];
+        const int ng = S.n_gates;
+        const bool first = si == 0 && (direct & kDirectFirst), last = si == n_sweeps - 1 && (direct & kDirectLast);
+        // both offsets of register index j combine per-bit parts: the LDS
+        // swizzle by XOR, the global offset by OR (disjoint bits)
+        uint32_t pb[W];
+        uint64_t gbit[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            pb[b] = lds_phys<T>(1u << S.qpos[b]);
+            gbit[b] = tile_offset(sp, 1u << S.qpos[b]);
+        }
+        auto goff_of = [&](int j) {
+            uint64_t o = 0;
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+                if ((j >> b) & 1) o |= gbit[b];
+            return o;
+        };
+        auto poff_of = [&](int j) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+                if ((j >> b) & 1) o ^= pb[b];
+            return o;
+        };
+        for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
+            const uint32_t gb = group_bits<W>(S, g);
+            const uint32_t pg = lds_phys<T>(gb);
+            cpx<T> *row = state + (base | tile_offset(sp, gb));
+            cpx<T> v[D];
+            if (first) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = row[goff_of(j)];
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = lds[pg ^ poff_of(j)];
+            }
+            for (int gi = 0; gi < ng; ++gi) sweep_gate_t<T, W, TWOQ>(v, gb, gates[goff + gi], base);
+            if (last) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) row[goff_of(j)] = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j) lds[pg ^ poff_of(j)] = v[j];
+            }
+        }
+        goff += ng;
+        __syncthreads();
+    }
+    if (!(direct & kDirectLast)) {
+        tile_store<T, kTileThreads, 8>(reinterpret_cast<V *>(state), lds, sp, base, 1u << m);
+        __syncthreads();
+    }
+}
+
 template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v, TileSpec sp, int m,
                                                        const TileSweep *__restrict__ sweeps, int n_sweeps,
                                                        const TileGate *__restrict__ gates,
-                                                       uint64_t n_tiles) {
-    using V = Vec<T>;
+                                                       uint64_t n_tiles, uint32_t direct) {
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
-    const uint32_t tsize = 1u << m;
+    cpx<T> *state = reinterpret_cast<cpx<T> *>(v);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        tile_load<T, kTileThreads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
-        tile_run_sweeps<T, W, TWOQ>(lds, m, base, sweeps, n_sweeps, gates);
-        tile_store<T, kTileThreads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
+        tile_pass_direct<T, W, TWOQ>(state, lds, sp, base, m, sweeps, n_sweeps, gates, direct);
     }
-    (void)sizeof(V);
 }
 
 template <typename T, int W, bool TWOQ>
 static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m, const TileSweep *sw,
-                          int n_sweeps, const TileGate *g, uint64_t n_tiles, size_t lds, hipStream_t s) {
+                          int n_sweeps, const TileGate *g, uint64_t n_tiles, uint32_t direct, size_t lds,
+                          hipStream_t s) {
     (void)hipFuncSetAttribute((const void *)k_tile<T, W, TWOQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 2048);
-    k_tile<T, W, TWOQ><<<grid, kTileThreads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles);
+    k_tile<T, W, TWOQ><<<grid, kTileThreads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles, direct);
 }
 
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, hipStream_t s) {
+                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, uint32_t direct,
+                       hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
     if (m > n || m > tile_max_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh || m < 1)
@@ -411,10 +481,10 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
     if (W == WW && two_qubit == Q) {                                                               \
         if (dtype == SV_C64)                                                                       \
             launch_tile_t<float, WW, Q>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,  \
-                                        n_tiles, lds, s);                                          \
+                                        n_tiles, direct, lds, s);                                  \
         else                                                                                       \
             launch_tile_t<double, WW, Q>((double2 *)amps, spec, m, dev_sweeps, n_sweeps,           \
-                                         dev_gates, n_tiles, lds, s);                              \
+                                         dev_gates, n_tiles, direct, lds, s);                      \
         return hipGetLastError();                                                                  \
     }
     SV_TILE_CASE(4, false)

@@ -298,6 +298,7 @@ struct PassCode {
     int m = 0;
     double flops_per_amp = 0.0; // algorithmic flops of the pass per state amplitude
     bool two_qubit = false;     // holds SK_2Q records
+    uint32_t direct = 0;        // kDirectFirst / kDirectLast (launch_tile)
     std::vector<TileSweep> sweeps;
     std::vector<TileGate> gates;
     size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + gates.size() * sizeof(TileGate); }
@@ -473,7 +474,9 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
     auto probe_of = [&](size_t i) -> const Probe * { return probes ? (*probes)[i] : nullptr; };
     auto close = [&]() {
         if (cur.empty()) return;
-        for (int b = 0; (int)qset.size() < W && b < pc.m; ++b)
+        // free register positions come from the top of the tile, leaving the
+        // low tile bits to the lanes (contiguous accesses)
+        for (int b = pc.m - 1; (int)qset.size() < W && b >= 0; --b)
             if (std::find(qset.begin(), qset.end(), b) == qset.end()) qset.push_back(b);
         std::sort(qset.begin(), qset.end());
         TileSweep sw{};
@@ -514,6 +517,10 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         cur.push_back(i);
     }
     close();
+    // the first and last sweeps read / write the state directly (measured
+    // faster than staging the tile through LDS for every register layout,
+    // most when the register positions leave the low tile bits to the lanes)
+    pc.direct = kDirectFirst | kDirectLast;
     return pc;
 }
 
@@ -529,7 +536,8 @@ static int launch_pass(sv_state *h, const PassCode &pc, size_t off) {
     const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + off +
                                                             align256(pc.sweeps.size() * sizeof(TileSweep)));
     Timed tm(h, K_TILE, 2.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
-    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, pc.two_qubit, h->stream));
+    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, pc.two_qubit, pc.direct,
+                       h->stream));
     return SV_OK;
 }
 

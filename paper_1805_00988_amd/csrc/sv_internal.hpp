@@ -138,9 +138,16 @@ hipError_t launch_gate2(void *amps, int n, int dtype, int t0, int t1, uint64_t c
                         const double *U, hipStream_t s);
 hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const double *factor,
                         hipStream_t s);
-// two_qubit: the pass holds SK_2Q records (selects the kernel instance with that path)
+// two_qubit: the pass holds SK_2Q records (selects the kernel instance with that
+// path).  direct: kDirectFirst / kDirectLast let the first sweep read its
+// register groups straight from the state / the last sweep write them straight
+// back instead of staging the tile through LDS (worth it when the sweep's
+// register positions leave the lowest tile bits to the lanes, so that a
+// wave's accesses stay contiguous).
+constexpr uint32_t kDirectFirst = 1, kDirectLast = 2;
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, hipStream_t s);
+                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, uint32_t direct,
+                       hipStream_t s);
 int tile_max_qubits(int dtype);
 int sweep_width(int dtype);
 // Dense blocks of a fused tile pass: positions of the block's qubits in the
