@@ -127,6 +127,35 @@ __device__ __forceinline__ void split4(const cpx<float> (&x)[4], bf16x8 &h, bf16
     }
 }
 
+// Where a block reads its operands and writes its results: the tile in LDS
+// (swizzled offsets qoff[2^K], goff = goff_lo[ROWS] then goff_hi) or the
+// state itself (global offsets gq, gg in the same layout, OR-combined with
+// the tile's base index).  The first block of a pass can read the state and
+// the last one write it, so that the tile crosses LDS only between blocks.
+struct BlockTabs {
+    const uint32_t *qoff, *goff;
+    const uint64_t *gq, *gg;
+};
+
+template <typename T, bool G>
+__device__ __forceinline__ cpx<T> blk_load(const cpx<T> *lds, const cpx<T> *state, uint32_t l, uint64_t g) {
+    if constexpr (G) return state[g];
+    else return lds[l];
+}
+template <typename T, bool G>
+__device__ __forceinline__ void blk_store(cpx<T> *lds, cpx<T> *state, uint32_t l, uint64_t g, cpx<T> x) {
+    if constexpr (G) state[g] = x;
+    else lds[l] = x;
+}
+
+// The MFMA operand lane layouts are mirror images (A lane l holds
+// A[l % R][k(l)], B lane l holds B[k(l)][l % R]), so the fragments, laid
+// out as the B operand of Y = X B, serve unchanged as the A operand of
+// Y^T = B^T X^T.  The kernels compute that transposed product: the result
+// a lane holds is then its own operand row (group), at block indices that
+// differ from its operand indices only in fixed bits, and a quarter-wave
+// writes consecutive groups.
+
 // complex64, split-BF16 (3 products, FP32 accumulate).  K = 4: 16x16x32,
 // one K-step; K = 5: 32x32x16, four K-steps.
 template <int K>
@@ -140,11 +169,11 @@ struct Bf16Cfg<5> {
     static constexpr int rows = 32, ksteps = 4, threads = 256;
 };
 
-// One block applied to the tile in LDS by this wave's wave-tiles.  f, qoff,
-// goff (goff_lo then goff_hi) point to the block's operand and tables.
-template <int K>
-__device__ __forceinline__ void block_bf16(cpx<float> *lds, const bf16x8 *f, const uint32_t *qoff,
-                                           const uint32_t *goff, uint32_t n_wt, int wave, int nwaves) {
+// One block applied to the tile by this wave's wave-tiles.  f points to the
+// block's operand fragments.
+template <int K, bool SG, bool DG>
+__device__ __forceinline__ void block_bf16(cpx<float> *lds, cpx<float> *state, uint64_t base, const bf16x8 *f,
+                                           const BlockTabs &t, uint32_t n_wt, int wave, int nwaves) {
     using C = Bf16Cfg<K>;
     constexpr int ROWS = C::rows, KS = C::ksteps;
     constexpr int ACC = ROWS == 32 ? 16 : 4;
@@ -158,42 +187,42 @@ __device__ __forceinline__ void block_bf16(cpx<float> *lds, const bf16x8 *f, con
         for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl) bw[p][s][hl] = f[((p * KS + s) * 2 + hl) * 64 + lane];
-    // lane (r, kk) reads amplitudes 8s + 4kk + i of row r; holds result
-    // rows 4kk + q (16x16) or 8(q/4) + 4kk + q%4 (32x32) of column r
-    const uint32_t a_lane = goff[r] ^ qoff[4 * kk];
-    const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
+    // lane (r, kk) reads block indices 4kk + 8s + i of row r and holds the
+    // results of row r at 4kk + q (16x16) or 4kk + 8(q/4) + q%4 (32x32)
+    const uint32_t l_lane = t.goff[r] ^ t.qoff[4 * kk];
+    const uint64_t g_lane = base | t.gg[r] | t.gq[4 * kk];
     for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-        const uint32_t gw = goff[ROWS + wt]; // goff_hi[wt]
-        const uint32_t pa = gw ^ a_lane;
+        const uint32_t lw = t.goff[ROWS + wt] ^ l_lane; // goff_hi[wt]
+        const uint64_t gw = t.gg[ROWS + wt] | g_lane;
         accT yr = {}, yi = {};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             cpx<float> x[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x[i] = lds[pa ^ qoff[8 * s + i]];
+            for (int i = 0; i < 4; ++i)
+                x[i] = blk_load<float, SG>(lds, state, lw ^ t.qoff[8 * s + i], gw | t.gq[8 * s + i]);
             bf16x8 h, l;
             split4(x, h, l);
             if constexpr (ROWS == 32) {
-                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][0], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][0], yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[0][s][1], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, bw[1][s][1], yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[0][s][0], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, bw[1][s][0], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[0][s][0], h, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[1][s][0], h, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[0][s][1], h, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[1][s][1], h, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[0][s][0], l, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bw[1][s][0], l, yi, 0, 0, 0);
             } else {
-                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][0], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][0], yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[0][s][1], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bw[1][s][1], yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[0][s][0], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bw[1][s][0], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[0][s][0], h, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[1][s][0], h, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[0][s][1], h, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[1][s][1], h, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[0][s][0], l, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[1][s][0], l, yi, 0, 0, 0);
             }
         }
-        const uint32_t po = gw ^ o_lane;
 #pragma unroll
         for (int q = 0; q < ACC; ++q) {
-            const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
-            lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
+            const int c = ROWS == 32 ? 8 * (q / 4) + (q % 4) : q;
+            blk_store<float, DG>(lds, state, lw ^ t.qoff[c], gw | t.gq[c], cpx<float>{yr[q], yi[q]});
         }
     }
 }
@@ -213,9 +242,9 @@ struct F32Cfg<5> {
     static constexpr int rows = 32, kps = 2, threads = 256;
 };
 
-template <int K>
-__device__ __forceinline__ void block_f32(cpx<float> *lds, const float *f, const uint32_t *qoff,
-                                          const uint32_t *goff, uint32_t n_wt, int wave, int nwaves) {
+template <int K, bool SG, bool DG>
+__device__ __forceinline__ void block_f32(cpx<float> *lds, cpx<float> *state, uint64_t base, const float *f,
+                                          const BlockTabs &t, uint32_t n_wt, int wave, int nwaves) {
     using C = F32Cfg<K>;
     constexpr int D = 1 << K, ROWS = C::rows, KPS = C::kps;
     constexpr int KS = 2 * D / KPS, HALF = KS / 2;
@@ -228,44 +257,46 @@ __device__ __forceinline__ void block_f32(cpx<float> *lds, const float *f, const
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int s = 0; s < KS; ++s) bw[p][s] = f[(p * KS + s) * 64 + lane];
-    const uint32_t a_lane = goff[r] ^ qoff[kk];
-    const uint32_t o_lane = goff[4 * kk] ^ qoff[r];
+    // reads: index kk + KPS*s of row r; results: 4kk + q (16x16) or
+    // 4kk + 8(q/4) + q%4 (32x32) of row r
+    const uint32_t la = t.goff[r] ^ t.qoff[kk], lo = t.goff[r] ^ t.qoff[4 * kk];
+    const uint64_t ga = base | t.gg[r] | t.gq[kk], go = base | t.gg[r] | t.gq[4 * kk];
     for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-        const uint32_t gw = goff[ROWS + wt]; // goff_hi[wt]
-        const uint32_t pa = gw ^ a_lane;
+        const uint32_t lh = t.goff[ROWS + wt];
+        const uint64_t gh = t.gg[ROWS + wt];
         accT yr = {}, yi = {};
 #pragma unroll
         for (int s = 0; s < HALF; ++s) {
-            const cpx<float> x = lds[pa ^ qoff[KPS * s]];
+            const cpx<float> x = blk_load<float, SG>(lds, state, lh ^ la ^ t.qoff[KPS * s], gh | ga | t.gq[KPS * s]);
             if constexpr (ROWS == 32) {
-                yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[0][s], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, bw[1][s], yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x2f32(bw[0][s], x.re, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x2f32(bw[1][s], x.re, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_32x32x2f32(bw[0][s + HALF], x.im, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_32x32x2f32(bw[1][s + HALF], x.im, yi, 0, 0, 0);
             } else {
-                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[0][s], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, bw[1][s], yi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[0][s + HALF], yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, bw[1][s + HALF], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(bw[0][s], x.re, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(bw[1][s], x.re, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(bw[0][s + HALF], x.im, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(bw[1][s + HALF], x.im, yi, 0, 0, 0);
             }
         }
-        const uint32_t po = gw ^ o_lane;
 #pragma unroll
         for (int q = 0; q < ACC; ++q) {
-            const uint32_t rq = ROWS == 32 ? 8u * (q / 4) + (q % 4) : (uint32_t)q;
-            lds[po ^ goff[rq]] = cpx<float>{yr[q], yi[q]};
+            const int c = ROWS == 32 ? 8 * (q / 4) + (q % 4) : q;
+            blk_store<float, DG>(lds, state, lh ^ lo ^ t.qoff[c], gh | go | t.gq[c], cpx<float>{yr[q], yi[q]});
         }
     }
 }
 
-// complex128 on the FP64 matrix cores (v_mfma_f64_16x16x4f64; operands laid
-// out as the FP32 16x16x4 ones, result element q of lane l is row 4q + l/16,
-// column l%16, as measured on the device): wave-tiles of 16 groups, D/16
-// output tiles of 16 amplitudes per part, K-steps as in the FP32 kernel.
-// Fragments stay in registers for K = 4 and are read per K-step for K = 5.
-template <int K>
-__device__ __forceinline__ void block_f64(cpx<double> *lds, const double *frag, const uint32_t *qoff,
-                                          const uint32_t *goff, uint32_t n_wt, int wave, int nwaves) {
+// complex128 on the FP64 matrix cores (v_mfma_f64_16x16x4f64; result
+// element q of lane l is row 4q + l/16, column l%16, as measured on the
+// device): wave-tiles of 16 groups, D/16 output tiles of 16 amplitudes per
+// part, K-steps as in the FP32 kernel.  Fragments stay in registers for
+// K = 4 and are read per K-step for K = 5.
+template <int K, bool SG, bool DG>
+__device__ __forceinline__ void block_f64(cpx<double> *lds, cpx<double> *state, uint64_t base,
+                                          const double *frag, const BlockTabs &t, uint32_t n_wt, int wave,
+                                          int nwaves) {
     constexpr int D = 1 << K;
     constexpr int NT = D / 16;
     constexpr int KS = 2 * D / 4;
@@ -278,11 +309,12 @@ __device__ __forceinline__ void block_f64(cpx<double> *lds, const double *frag, 
 #pragma unroll
         for (int i = 0; i < 2 * NT * KS; ++i) bpre[i] = frag[i * 64 + lane];
     }
-    const uint32_t a_lane = goff[r] ^ qoff[kk];
-    const uint32_t o_lane = goff[kk] ^ qoff[r];
+    // reads: index kk + 4s of row r; results: kk + 4q + 16nt of row r
+    const uint32_t l_lane = t.goff[r] ^ t.qoff[kk];
+    const uint64_t g_lane = base | t.gg[r] | t.gq[kk];
     for (uint32_t wt = wave; wt < n_wt; wt += nwaves) {
-        const uint32_t gw = goff[16 + wt]; // goff_hi[wt]
-        const uint32_t pa = gw ^ a_lane;
+        const uint32_t lw = t.goff[16 + wt] ^ l_lane; // goff_hi[wt]
+        const uint64_t gw = t.gg[16 + wt] | g_lane;
         doublex4 acc[2][NT];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -290,7 +322,7 @@ __device__ __forceinline__ void block_f64(cpx<double> *lds, const double *frag, 
             for (int nt = 0; nt < NT; ++nt) acc[p][nt] = doublex4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < HALF; ++s) {
-            const cpx<double> x = lds[pa ^ qoff[4 * s]];
+            const cpx<double> x = blk_load<double, SG>(lds, state, lw ^ t.qoff[4 * s], gw | t.gq[4 * s]);
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -298,16 +330,18 @@ __device__ __forceinline__ void block_f64(cpx<double> *lds, const double *frag, 
                     const int i0 = (p * NT + nt) * KS + s, i1 = i0 + HALF;
                     const double b0 = PRELOAD ? bpre[PRELOAD ? i0 : 0] : frag[i0 * 64 + lane];
                     const double b1 = PRELOAD ? bpre[PRELOAD ? i1 : 0] : frag[i1 * 64 + lane];
-                    acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, b0, acc[p][nt], 0, 0, 0);
-                    acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, b1, acc[p][nt], 0, 0, 0);
+                    acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, x.re, acc[p][nt], 0, 0, 0);
+                    acc[p][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, x.im, acc[p][nt], 0, 0, 0);
                 }
         }
-        const uint32_t po = gw ^ o_lane;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                lds[po ^ goff[4 * q] ^ qoff[16 * nt]] = cpx<double>{acc[0][nt][q], acc[1][nt][q]};
+            for (int q = 0; q < 4; ++q) {
+                const int c = 4 * q + 16 * nt;
+                blk_store<double, DG>(lds, state, lw ^ t.qoff[c], gw | t.gq[c],
+                                      cpx<double>{acc[0][nt][q], acc[1][nt][q]});
+            }
     }
 }
 
@@ -321,41 +355,57 @@ struct EngCfg {
     static constexpr int threads = ENG == kPrecMfma64 ? 256 : (K == 5 ? 256 : 512);
 };
 
-template <int ENG, int K>
-__device__ __forceinline__ void apply_block(cpx<typename EngCfg<ENG, K>::T> *lds, const char *op,
-                                            const uint32_t *tab, uint32_t n_wt, int wave, int nwaves) {
-    const uint32_t *qoff = tab, *goff = tab + (1 << K);
+template <int ENG, int K, bool SG, bool DG>
+__device__ __forceinline__ void apply_block_t(cpx<typename EngCfg<ENG, K>::T> *lds,
+                                              cpx<typename EngCfg<ENG, K>::T> *state, uint64_t base,
+                                              const char *op, const BlockTabs &t, uint32_t n_wt, int wave,
+                                              int nwaves) {
     if constexpr (ENG == SV_PREC_SPLIT_BF16)
-        block_bf16<K>(lds, reinterpret_cast<const bf16x8 *>(op), qoff, goff, n_wt, wave, nwaves);
+        block_bf16<K, SG, DG>(lds, state, base, reinterpret_cast<const bf16x8 *>(op), t, n_wt, wave, nwaves);
     else if constexpr (ENG == SV_PREC_FP32)
-        block_f32<K>(lds, reinterpret_cast<const float *>(op), qoff, goff, n_wt, wave, nwaves);
+        block_f32<K, SG, DG>(lds, state, base, reinterpret_cast<const float *>(op), t, n_wt, wave, nwaves);
     else
-        block_f64<K>(lds, reinterpret_cast<const double *>(op), qoff, goff, n_wt, wave, nwaves);
+        block_f64<K, SG, DG>(lds, state, base, reinterpret_cast<const double *>(op), t, n_wt, wave, nwaves);
 }
 
 template <int ENG, int K>
 __global__ __launch_bounds__((EngCfg<ENG, K>::threads)) void k_dense_mfma(
     typename Amp16<typename EngCfg<ENG, K>::T>::type *v, TileSpec sp, int m, const DenseBlock *__restrict__ blocks,
-    int n_blocks, const char *__restrict__ base_ptr, uint64_t n_tiles) {
+    int n_blocks, const char *__restrict__ base_ptr, uint64_t n_tiles, uint32_t direct) {
     using Cf = EngCfg<ENG, K>;
     using T = typename Cf::T;
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
+    cpx<T> *state = reinterpret_cast<cpx<T> *>(v);
     const uint32_t tsize = 1u << m;
     const uint32_t n_wt = (tsize >> K) / Cf::rows;
     const int wave = wave_id(), nwaves = Cf::threads / 64;
+    const bool dfirst = direct & kDirectFirst, dlast = direct & kDirectLast;
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t base = tile_base(sp, tile);
-        tile_load<T, Cf::threads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
-        for (int b = 0; b < n_blocks; ++b) {
-            const DenseBlock &B = blocks[b];
-            apply_block<ENG, K>(lds, base_ptr + B.op_off, reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off),
-                                n_wt, wave, nwaves);
+        if (!dfirst) {
+            tile_load<T, Cf::threads, 8>(v, lds, sp, base, tsize);
             __syncthreads();
         }
-        tile_store<T, Cf::threads, 8>(v, lds, sp, base, tsize);
-        __syncthreads();
+        for (int b = 0; b < n_blocks; ++b) {
+            const DenseBlock &B = blocks[b];
+            const uint32_t *tab = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
+            const uint64_t *gtab = reinterpret_cast<const uint64_t *>(base_ptr + B.gtab_off);
+            const BlockTabs t{tab, tab + (1 << K), gtab, gtab + (1 << K)};
+            const char *op = base_ptr + B.op_off;
+            const bool sg = b == 0 && dfirst, dg = b == n_blocks - 1 && dlast;
+            if (sg && dg) apply_block_t<ENG, K, true, true>(lds, state, base, op, t, n_wt, wave, nwaves);
+            else if (sg) apply_block_t<ENG, K, true, false>(lds, state, base, op, t, n_wt, wave, nwaves);
+            else if (dg) apply_block_t<ENG, K, false, true>(lds, state, base, op, t, n_wt, wave, nwaves);
+            else apply_block_t<ENG, K, false, false>(lds, state, base, op, t, n_wt, wave, nwaves);
+            // the next block (or the next tile's first LDS writes) follows
+            // every wave's reads of this one
+            __syncthreads();
+        }
+        if (!dlast) {
+            tile_store<T, Cf::threads, 8>(v, lds, sp, base, tsize);
+            __syncthreads();
+        }
     }
 }
 
@@ -364,7 +414,7 @@ int fused_tile_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
 
 hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, int k,
                              const DenseBlock *dev_blocks, int n_blocks, const char *dev_base, int prec,
-                             hipStream_t s) {
+                             uint32_t direct, hipStream_t s) {
     const int m = sp.L + sp.K;
     if (m > n || k > m || k < 1 || k > 5 || n_blocks < 1) return hipErrorInvalidValue;
     const uint64_t n_tiles = 1ull << (n - m);
@@ -381,7 +431,8 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
         (void)hipFuncSetAttribute((const void *)k_dense_mfma<ENG, KK>,                             \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
         k_dense_mfma<ENG, KK><<<grid, EngCfg<ENG, KK>::threads, lds, s>>>((VT *)amps, sp, m, dev_blocks, \
-                                                                         n_blocks, dev_base, n_tiles); \
+                                                                         n_blocks, dev_base, n_tiles, \
+                                                                         direct);                      \
         return hipGetLastError();                                                                  \
     }
         SV_MFMA_CASE(SV_PREC_SPLIT_BF16, 4)

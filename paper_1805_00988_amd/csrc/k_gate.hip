@@ -351,7 +351,10 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
 // tile and tested once on its base index.
 constexpr int kTileThreads = 512;
 
-int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; } // 64 KiB of LDS
+// 64 KiB of LDS, two workgroups per CU.  (Tiles of 128 KiB with 1024 threads
+// took fewer passes but more time per gate: slower overall.)
+int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
+int batch_tile_qubits(int dtype) { return tile_max_qubits(dtype); }
 
 // Register qubits per sweep: 16 complex64 or 8 complex128 amplitudes per
 // group (64 and 32 VGPRs), keeping two 512-thread workgroups per CU.

@@ -405,9 +405,11 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
         r.b0 = pos(g.t[0]);
         bool real = true;
         for (int i = 0; i < 4; ++i) real = real && g.U[2 * i + 1] == 0.0;
+        // real diagonal, imaginary off-diagonal: half the arithmetic of a general matrix
+        const bool rimag = g.U[1] == 0.0 && g.U[7] == 0.0 && g.U[2] == 0.0 && g.U[4] == 0.0;
         encode_sweep_masks(qset, cin, 1u << r.b0, 0, &r);
         // an exchange with per-lane controls runs as the real matrix X
-        r.kind = is_x(g) && r.lane == 0 ? SK_SWAP : (real ? SK_REAL : SK_GEN);
+        r.kind = is_x(g) && r.lane == 0 ? SK_SWAP : (real ? SK_REAL : (rimag ? SK_RIMAG : SK_GEN));
         put_matrix(r, g.U, 4, f32);
         return r;
     }
@@ -620,6 +622,8 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         return SV_OK;
     }
     const int mmax = std::min(h->n, tile_max_qubits(h->dtype));
+    // runs of 128 complex64 / 64 complex128 amplitudes: shorter runs cut
+    // the number of passes but cost more per pass (measured)
     const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
     std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin);
     // compile every tiled pass, stage all of them, upload once, launch in order
@@ -867,6 +871,7 @@ struct FusedPass {
     double flops_per_amp = 0.0; // 8 * 2^k per block of k qubits (complex matvec as real flops)
     int k = 0;
     int engine = SV_PREC_NATIVE;
+    uint32_t direct = 0; // kDirectFirst / kDirectLast (matrix cores)
     std::vector<DenseBlock> blocks;
     std::vector<std::vector<std::complex<double>>> mats;
 };
@@ -886,14 +891,27 @@ static size_t dense_frag_bytes(const sv_state *h, int k, int engine) {
 static int mfma_rows(int k, int engine) { return engine == kPrecMfma64 ? 16 : (k == 5 ? 32 : 16); }
 
 // operand plus, for the matrix cores, the LDS offset tables
-// (qoff[2^k], goff_lo[rows], goff_hi[2^(m-k) / rows])
+// (qoff[2^k], goff_lo[rows], goff_hi[2^(m-k) / rows]) and the same tables of
+// global offsets
+static size_t dense_tab_entries(int k, int m, int engine) {
+    const size_t rows = (size_t)mfma_rows(k, engine);
+    return ((size_t)1 << k) + rows + (((size_t)1 << (m - k)) / rows);
+}
 static size_t dense_op_bytes(const sv_state *h, int k, int m, int engine) {
     size_t b = dense_frag_bytes(h, k, engine);
     if (is_mfma(engine)) {
-        const size_t rows = (size_t)mfma_rows(k, engine);
-        b += align256((((size_t)1 << k) + rows + (((size_t)1 << (m - k)) / rows)) * sizeof(uint32_t));
+        b += align256(dense_tab_entries(k, m, engine) * sizeof(uint32_t));
+        b += align256(dense_tab_entries(k, m, engine) * sizeof(uint64_t));
     }
     return b;
+}
+
+// Global index offset (from the tile's base) of local tile index l.
+static uint64_t tile_global_offset(const TileSpec &sp, uint32_t l) {
+    uint64_t g = l & ((1u << sp.L) - 1u);
+    for (int i = 0; i < sp.K; ++i)
+        if ((l >> (sp.L + i)) & 1u) g |= 1ull << sp.high[i];
+    return g;
 }
 
 static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp) {
@@ -912,7 +930,11 @@ static std::vector<std::complex<double>> pad_matrix(const std::vector<std::compl
 }
 
 // Shortest contiguous run (low tile qubits) of a fused pass: 512 bytes.
-static int fused_lmin(const sv_state *h) { return std::min(h->n, h->dtype == SV_C64 ? 6 : 5); }
+// fused passes take every qubit of a gate into the tile, so they need more
+// passes than the tile scheduler's target-only masks; runs of 32 amplitudes
+// (256 bytes complex64, 512 complex128) balance the pass count against the
+// cost per pass (measured on complex64)
+static int fused_lmin(const sv_state *h) { return std::min(h->n, 5); }
 
 // One fused pass over the blocks bs[idx] (all their qubits fit in one tile).
 // Blocks run on the matrix cores in the requested precision (the state's own
@@ -938,6 +960,9 @@ static FusedPass build_fused_pass(const sv_state *h, const std::vector<Block> &b
         fp.engine = mfma64_ok(h, K) ? kPrecMfma64 : SV_PREC_NATIVE;
     }
     fp.k = fp.engine == SV_PREC_NATIVE ? kmax : K;
+    // the matrix-core kernels read the first block's operands from the state
+    // and write the last block's results back to it
+    if (is_mfma(fp.engine)) fp.direct = kDirectFirst | kDirectLast;
     for (int bi : idx) {
         const Block &B = bs[bi];
         DenseBlock db{};
@@ -1012,6 +1037,7 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
         DenseBlock &db = fp.blocks[b];
         db.op_off = (int64_t)opo;
         db.tab_off = 0;
+        db.gtab_off = 0;
         char *dst = h->h_arena + opo;
         const std::complex<double> *U = fp.mats[b].data();
         if (fp.engine == kPrecMfma64) {
@@ -1047,6 +1073,14 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
             for (uint32_t g = 0; g < rows; ++g) goff[g] = lds_swizzle(deposit(g, db.bp.gpos, db.bp.ng), ab);
             for (uint32_t w = 0; w < (1u << (fp.m - fp.k)) / rows; ++w)
                 ghi[w] = lds_swizzle(deposit(w * rows, db.bp.gpos, db.bp.ng), ab);
+            // the same tables as global offsets
+            db.gtab_off = (int64_t)(opo + fb + align256(dense_tab_entries(fp.k, fp.m, fp.engine) * sizeof(uint32_t)));
+            uint64_t *gq = reinterpret_cast<uint64_t *>(h->h_arena + db.gtab_off);
+            uint64_t *gg = gq + (1u << fp.k);
+            for (uint32_t j = 0; j < (1u << fp.k); ++j) gq[j] = tile_global_offset(fp.sp, deposit(j, db.bp.qpos, fp.k));
+            for (uint32_t g = 0; g < rows; ++g) gg[g] = tile_global_offset(fp.sp, deposit(g, db.bp.gpos, db.bp.ng));
+            for (uint32_t w = 0; w < (1u << (fp.m - fp.k)) / rows; ++w)
+                gg[rows + w] = tile_global_offset(fp.sp, deposit(w * rows, db.bp.gpos, db.bp.ng));
         }
     }
     std::memcpy(h->h_arena + off, fp.blocks.data(), fp.blocks.size() * sizeof(DenseBlock));
@@ -1056,7 +1090,7 @@ static int launch_fused(sv_state *h, const FusedPass &fp, size_t off) {
     Timed tm(h, K_FUSED, 2.0 * state_bytes(h), fp.flops_per_amp * (double)(1ull << h->n));
     SV_HIP(launch_dense_pass(h->amps, h->n, h->dtype, fp.sp, fp.k,
                              reinterpret_cast<const DenseBlock *>(h->d_arena + off), (int)fp.blocks.size(),
-                             h->d_arena, fp.engine, h->stream));
+                             h->d_arena, fp.engine, fp.direct, h->stream));
     return SV_OK;
 }
 
@@ -1928,7 +1962,7 @@ int sv_batch_create(int n_circuits, const int *widths, const int64_t *op_offsets
         sv_batch_free(b);
         return hip_fail(e, "sv_batch_create");
     }
-    const int rc = batch_prepare(b, tile_max_qubits(dtype), sweep_width(dtype), 2 * device_cus());
+    const int rc = batch_prepare(b, batch_tile_qubits(dtype), sweep_width(dtype), 2 * device_cus());
     if (rc) {
         const std::string msg = g_last_error;
         sv_batch_free(b);
@@ -1966,7 +2000,7 @@ int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *g
     if (!b) return fail(SV_EINVAL, "NULL batch");
     if (reps < 1) reps = 1;
     const int cus = device_cus();
-    const int mtop = tile_max_qubits(b->dtype);
+    const int mtop = batch_tile_qubits(b->dtype);
     const int ws[2] = {3, 4};
     const int ms[3] = {mtop, mtop - 1, mtop - 2};
     const int gs[2] = {cus, 2 * cus};

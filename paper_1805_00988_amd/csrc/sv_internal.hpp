@@ -81,7 +81,9 @@ enum SweepKind : int32_t {
     SK_2Q = 5,    // 4x4 on sweep positions b0 < b1 (bit 0 of the matrix index <-> b0)
     SK_PARAM = 6, // adjoint sweep: add Im<lam|M|psi> for M (entries 0-3) on position b0
                   // to slot b1; the undo of the gate follows as its own record
-    SK_DIAGR = 7  // diag(d0, d1) on sweep position b0; m: d0, d1
+    SK_DIAGR = 7, // diag(d0, d1) on sweep position b0; m: d0, d1
+    SK_RIMAG = 8  // 2x2 on sweep position b0 with real diagonal and imaginary
+                  // off-diagonal entries (RX, Y); m: the four complex entries
 };
 // Controls inside the tile are split by where they sit in the sweep: bits
 // on tile positions outside the registers ('lane') are constant over one
@@ -149,6 +151,7 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
                        int n_sweeps, const TileGate *dev_gates, bool two_qubit, uint32_t direct,
                        hipStream_t s);
 int tile_max_qubits(int dtype);
+int batch_tile_qubits(int dtype);
 int sweep_width(int dtype);
 // Dense blocks of a fused tile pass: positions of the block's qubits in the
 // tile (bit j of the matrix index <-> qpos[j]) and of the remaining tile bits
@@ -165,18 +168,23 @@ struct BlockPos {
 // qpos, then goff_lo[R] and goff_hi[2^(m-k) / R] = the same for group index
 // g (g < R) and g = w * R deposited at gpos, R the kernel's MFMA rows.  The
 // maps are linear over XOR, so the offset of (group w*R + i, index j) is
-// goff_hi[w] ^ goff_lo[i] ^ qoff[j].
+// goff_hi[w] ^ goff_lo[i] ^ qoff[j].  gtab_off: the same three tables as
+// uint64 global index offsets from the tile's base (OR-combined), for the
+// blocks that read or write the state directly.
 struct DenseBlock {
     BlockPos bp;
     int32_t pad;
     int64_t op_off;
     int64_t tab_off;
+    int64_t gtab_off;
 };
 // launch_dense_pass precision code for complex128 blocks on the FP64 matrix cores
 constexpr int kPrecMfma64 = 100;
+// direct (matrix cores): kDirectFirst / kDirectLast let the first block read
+// the state and the last block write it without staging the tile in LDS
 hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, int k,
                              const DenseBlock *dev_blocks, int n_blocks, const char *dev_base, int prec,
-                             hipStream_t s);
+                             uint32_t direct, hipStream_t s);
 int fused_tile_qubits(int dtype);
 hipError_t launch_probabilities(const void *amps, int n, int dtype, void *dev_out,
                                 double *dev_partials, int n_partials, double *dev_total,

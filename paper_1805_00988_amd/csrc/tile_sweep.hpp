@@ -206,6 +206,22 @@ __device__ __forceinline__ T gre(const TileGate &G, int i) {
                        "=&v"(br), "=&v"(bi)),                                                      \
                SV_INS("v"(r[0]), "v"(r[1]), "v"(r[2]), "v"(r[3])));                                \
     }                                                                                              \
+    /* (x0, x1) <- (r0 x0 + i q1 x1, i q2 x0 + r3 x1), r, q real: w = {r0, q1, q2, r3} */          \
+    template <int J, bool TEST>                                                                    \
+    __device__ __forceinline__ void rrimag(cpx<T> &x0, cpx<T> &x1, const T (&w)[4], uint32_t am) { \
+        T ar, ai, br, bi;                                                                          \
+        SV_ASM("v_mul_" S " %4, -%9, %3\n\t"                                                       \
+               "v_mul_" S " %5, %9, %2\n\t"                                                        \
+               "v_mul_" S " %6, -%10, %1\n\t"                                                      \
+               "v_mul_" S " %7, %10, %0\n\t"                                                       \
+               "v_fma_" S " %0, %8, %0, %4\n\t"                                                    \
+               "v_fma_" S " %1, %8, %1, %5\n\t"                                                    \
+               "v_fma_" S " %2, %11, %2, %6\n\t"                                                   \
+               "v_fma_" S " %3, %11, %3, %7",                                                      \
+               SV_OUTS("+v"(x0.re), "+v"(x0.im), "+v"(x1.re), "+v"(x1.im), "=&v"(ar), "=&v"(ai),    \
+                       "=&v"(br), "=&v"(bi)),                                                      \
+               SV_INS("v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3])));                                \
+    }                                                                                              \
     /* x <- dr x + a (dr real) */                                                                  \
     template <int J, bool TEST>                                                                    \
     __device__ __forceinline__ void rfin(cpx<T> &x, T dr, cpx<T> a, uint32_t am) {                 \
@@ -311,6 +327,10 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], bool ok, const Gat
         const T r[4] = {ok ? hre<T>(h, 0) : T(1), ok ? hre<T>(h, 1) : T(0), ok ? hre<T>(h, 2) : T(0),
                         ok ? hre<T>(h, 3) : T(1)};
         over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rreal<j, t>(v[j], v[j | (1 << P)], r, am); });
+    } else if (kind == SK_RIMAG) {
+        const cpx<T> m1 = hmat<T>(h, 1), m2 = hmat<T>(h, 2);
+        const T w[4] = {ok ? hre<T>(h, 0) : T(1), ok ? m1.im : T(0), ok ? m2.im : T(0), ok ? hre<T>(h, 3) : T(1)};
+        over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rrimag<j, t>(v[j], v[j | (1 << P)], w, am); });
     } else if (kind == SK_SWAP) { // never carries per-lane controls
         over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rswap<j, t>(v[j], v[j | (1 << P)], am); });
     } else { // SK_DIAGR: amplitude j takes d1 if its bit P is set, else d0
