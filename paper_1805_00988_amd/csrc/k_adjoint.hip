@@ -171,7 +171,7 @@ __device__ __forceinline__ double probe_gate(const cpx<T> (&v)[1 << W], const cp
 template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::type *psi, typename AV<T>::type *lam,
                                                       TileSpec sp, int m, const TileSweep *__restrict__ sweeps,
-                                                      int n_sweeps, const TileGate *__restrict__ gates,
+                                                      int n_sweeps, const char *__restrict__ recs,
                                                       int slot0, int n_slots, double *partials,
                                                       uint64_t n_tiles) {
     constexpr int D = 1 << W;
@@ -188,7 +188,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
         tile_load<T, kAdjThreads, 4>(psi, lp, sp, base, tsize);
         tile_load<T, kAdjThreads, 4>(lam, ll, sp, base, tsize);
         __syncthreads();
-        int goff = 0;
         for (int si = 0; si < n_sweeps; ++si) {
             const TileSweep &S = sweeps[si];
             const int ng = S.n_gates;
@@ -202,21 +201,27 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                 const uint32_t gb = group_bits<W>(S, act ? g : 0u);
                 const uint32_t pg = lds_phys<T>(gb);
                 cpx<T> v[D], w[D];
+                PhaseAcc<T, W> acc_unused;
+                acc_unused.init();
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     v[j] = lp[pg ^ PF[j]];
                     w[j] = ll[pg ^ PF[j]];
                 }
+                const char *rp = recs + S.rec_off;
                 for (int gi = 0; gi < ng; ++gi) {
-                    const TileGate &G = gates[goff + gi];
+                    const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
+                    rp += G.size;
                     if (G.kind == SK_PARAM) {
                         if ((base & G.cout) != G.cout) continue; // uniform
                         const double mine = act ? probe_gate<T, W>(v, w, gb, G) : 0.0;
                         const double c = wave_sum_d(mine);
                         if ((threadIdx.x & 63) == 0) atomicAdd(&slot_acc[G.b1], c);
                     } else {
-                        sweep_gate_t<T, W, TWOQ>(v, gb, G, base);
-                        sweep_gate_t<T, W, TWOQ>(w, gb, G, base);
+                        // adjoint passes carry no gathered phases (their
+                        // probes read the amplitudes between gates)
+                        sweep_gate_t<T, W, TWOQ>(v, acc_unused, gb, G, base);
+                        sweep_gate_t<T, W, TWOQ>(w, acc_unused, gb, G, base);
                     }
                 }
                 if (act) {
@@ -227,7 +232,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                     }
                 }
             }
-            goff += ng;
             __syncthreads();
         }
         tile_store<T, kAdjThreads, 4>(psi, lp, sp, base, tsize);
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
 }
 
 hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,
-                               const TileSweep *dev_sweeps, int n_sweeps, const TileGate *dev_gates,
+                               const TileSweep *dev_sweeps, int n_sweeps, const char *dev_gates,
                                int slot0, int n_slots, double *partials, int n_blocks, bool two_qubit,
                                hipStream_t s) {
     const int m = spec.L + spec.K;

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
                 }
                 __syncthreads();
                 tile_run_sweeps<T, W, TWOQ>(lds, m, base, a.sweeps + p.sweep_off, p.n_sweeps,
-                                      a.gates + p.gate_off);
+                                      a.recs + p.gate_off);
                 if (last) {
                     for (uint32_t l = threadIdx.x; l < tsize; l += kBatchThreads)
                         zacc += zterm(lds[lds_phys<T>(l)], btile_addr(p.sp, base, l), a.zmask);

@@ -379,7 +379,7 @@ __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t bas
 template <typename T, int W, bool TWOQ>
 __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const TileSpec &sp, uint64_t base,
                                  int m, const TileSweep *__restrict__ sweeps, int n_sweeps,
-                                 const TileGate *__restrict__ gates, uint32_t direct) {
+                                 const char *__restrict__ recs, uint32_t direct) {
     constexpr int D = 1 << W;
     const uint32_t n_groups = (1u << m) >> W;
     using V = typename Vec<T>::type;
@@ -387,7 +387,6 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
         tile_load<T, kTileThreads, 8>(reinterpret_cast<const V *>(state), lds, sp, base, 1u << m);
         __syncthreads();
     }
-    int goff = 0;
     for (int si = 0; si < n_sweeps; ++si) {
         const TileSweep &S = sweeps[si];
         const int ng = S.n_gates;
@@ -427,7 +426,14 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
 #pragma unroll
                 for (int j = 0; j < D; ++j) v[j] = lds[pg ^ poff_of(j)];
             }
-            for (int gi = 0; gi < ng; ++gi) sweep_gate_t<T, W, TWOQ>(v, gb, gates[goff + gi], base);
+            PhaseAcc<T, W> acc;
+            acc.init();
+            const char *rp = recs + S.rec_off;
+            for (int gi = 0; gi < ng; ++gi) {
+                const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
+                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+                rp += G.size;
+            }
             if (last) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) row[goff_of(j)] = v[j];
@@ -436,7 +442,6 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
                 for (int j = 0; j < D; ++j) lds[pg ^ poff_of(j)] = v[j];
             }
         }
-        goff += ng;
         __syncthreads();
     }
     if (!(direct & kDirectLast)) {
@@ -448,7 +453,7 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
 template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v, TileSpec sp, int m,
                                                        const TileSweep *__restrict__ sweeps, int n_sweeps,
-                                                       const TileGate *__restrict__ gates,
+                                                       const char *__restrict__ recs,
                                                        uint64_t n_tiles, uint32_t direct) {
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
@@ -456,13 +461,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v,
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        tile_pass_direct<T, W, TWOQ>(state, lds, sp, base, m, sweeps, n_sweeps, gates, direct);
+        tile_pass_direct<T, W, TWOQ>(state, lds, sp, base, m, sweeps, n_sweeps, recs, direct);
     }
 }
 
 template <typename T, int W, bool TWOQ>
 static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m, const TileSweep *sw,
-                          int n_sweeps, const TileGate *g, uint64_t n_tiles, uint32_t direct, size_t lds,
+                          int n_sweeps, const char *g, uint64_t n_tiles, uint32_t direct, size_t lds,
                           hipStream_t s) {
     (void)hipFuncSetAttribute((const void *)k_tile<T, W, TWOQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -471,7 +476,7 @@ static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m,
 }
 
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, uint32_t direct,
+                       int n_sweeps, const char *dev_gates, bool two_qubit, uint32_t direct,
                        hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;

@@ -300,9 +300,39 @@ struct PassCode {
     bool two_qubit = false;     // holds SK_2Q records
     uint32_t direct = 0;        // kDirectFirst / kDirectLast (launch_tile)
     std::vector<TileSweep> sweeps;
-    std::vector<TileGate> gates;
-    size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + gates.size() * sizeof(TileGate); }
+    std::vector<TileGate> gates; // records in sweep order (host form)
+    std::vector<char> recs;      // the same, packed for the device (pack_records)
+    size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + recs.size(); }
 };
+
+// Complex matrix entries a record kind reads on the device.
+static int record_entries(int kind) {
+    switch (kind) {
+    case SK_2Q: return 16;
+    case SK_GEN: case SK_REAL: case SK_RIMAG: case SK_PARAM: return 4;
+    case SK_DIAG: case SK_DIAGR: return 2;
+    case SK_PHASE: return 1;
+    default: return 0; // SK_SWAP, SK_FLUSH
+    }
+}
+
+// Pack the records (each cut after its entries, 8-byte aligned sizes) and
+// point every sweep at its first record.
+static void pack_records(PassCode &pc, bool f32) {
+    pc.recs.clear();
+    size_t gi = 0;
+    for (TileSweep &S : pc.sweeps) {
+        S.rec_off = (int32_t)pc.recs.size();
+        for (int k = 0; k < S.n_gates; ++k, ++gi) {
+            TileGate r = pc.gates[gi];
+            const size_t sz = ((size_t)kRecordHead + (size_t)record_entries(r.kind) * (f32 ? 8 : 16) + 7) & ~(size_t)7;
+            r.size = (int32_t)sz;
+            const char *src = reinterpret_cast<const char *>(&r);
+            pc.recs.insert(pc.recs.end(), src, src + sz);
+        }
+    }
+    pc.recs.resize(pc.recs.size() + kRecordTail, 0);
+}
 
 static bool is_diag1(const Gate &g) { return g.k == 1 && is_zero(g.U + 2) && is_zero(g.U + 4); }
 
@@ -465,6 +495,10 @@ static TileGate encode_probe(const TileSpec &sp, const std::vector<int> &qset, c
 // target, since they act per amplitude.  With probes (adjoint passes), a
 // parametrised gate needs its target in registers and is encoded as a probe
 // record followed by its own record.
+// shortest run of phase gates gathered into per-lane factors (a flush costs
+// about as much as applying three of them one by one)
+constexpr int kMinPhaseRun = 4;
+
 static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w, bool f32,
                              const std::vector<const Probe *> *probes = nullptr) {
     PassCode pc;
@@ -483,7 +517,60 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         std::sort(qset.begin(), qset.end());
         TileSweep sw{};
         sw.n_gates = 0;
-        for (size_t i : cur) {
+        const uint32_t fall = register_bits(qset, (1 << qset.size()) - 1);
+        // Phase gates whose condition holds at most one register bit are
+        // gathered into per-lane factors (all diagonal gates commute) when at
+        // least kMinPhaseRun of them follow each other; a flush applies them.
+        std::vector<int> slot(cur.size(), -1);
+        if (!probes) {
+            for (size_t a = 0; a < cur.size();) {
+                size_t b = a;
+                while (b < cur.size()) {
+                    const Gate &g = *gs[cur[b]];
+                    if (!is_diag1(g) || !is_one(g.U)) break;
+                    TileGate tmp{};
+                    const uint32_t cond = encode_controls(sp, g.ctrl, &tmp) | (1u << local_bit(sp, g.t[0]));
+                    const uint32_t reg = cond & fall;
+                    if (__builtin_popcount(reg) > 1) break;
+                    int s = W;
+                    for (int q = 0; q < W; ++q)
+                        if (reg == (1u << qset[q])) s = q;
+                    slot[b] = s;
+                    ++b;
+                }
+                if (b - a < (size_t)kMinPhaseRun)
+                    for (size_t c = a; c < b; ++c) slot[c] = -1;
+                a = b == a ? a + 1 : b;
+            }
+        }
+        uint32_t pending = 0;
+        auto flush = [&]() {
+            if (!pending) return;
+            TileGate r{};
+            r.kind = SK_FLUSH;
+            r.amask = pending;
+            pc.gates.push_back(r);
+            ++sw.n_gates;
+            pending = 0;
+        };
+        for (size_t ci = 0; ci < cur.size(); ++ci) {
+            const size_t i = cur[ci];
+            if (slot[ci] >= 0) {
+                const Gate &g = *gs[i];
+                TileGate r{};
+                const uint32_t cond = encode_controls(sp, g.ctrl, &r) | (1u << local_bit(sp, g.t[0]));
+                r.kind = SK_PHASE;
+                r.b0 = slot[ci];
+                r.lane = cond & ~fall;
+                r.amask = 1;
+                put_matrix(r, g.U + 6, 1, f32);
+                pc.gates.push_back(r);
+                ++sw.n_gates;
+                pending |= 1u << slot[ci];
+                pc.flops_per_amp += gate_flops_per_amp(g);
+                continue;
+            }
+            flush();
             if (const Probe *pr = probe_of(i)) {
                 pc.gates.push_back(encode_probe(sp, qset, *gs[i], *pr, f32));
                 ++sw.n_gates;
@@ -495,6 +582,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
             ++sw.n_gates;
             pc.flops_per_amp += (probes ? 2.0 : 1.0) * gate_flops_per_amp(*gs[i]);
         }
+        flush();
         for (int j = 0; j < kSweepW; ++j) sw.qpos[j] = j < W ? qset[j] : 0;
         pc.sweeps.push_back(sw);
         cur.clear();
@@ -519,6 +607,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         cur.push_back(i);
     }
     close();
+    pack_records(pc, f32);
     // the first and last sweeps read / write the state directly (measured
     // faster than staging the tile through LDS for every register layout,
     // most when the register positions leave the low tile bits to the lanes)
@@ -529,14 +618,13 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
 // Write a compiled pass into the host arena at 'off' (256-aligned).
 static void stage_pass(sv_state *h, const PassCode &pc, size_t off) {
     std::memcpy(h->h_arena + off, pc.sweeps.data(), pc.sweeps.size() * sizeof(TileSweep));
-    std::memcpy(h->h_arena + off + align256(pc.sweeps.size() * sizeof(TileSweep)), pc.gates.data(),
-                pc.gates.size() * sizeof(TileGate));
+    std::memcpy(h->h_arena + off + align256(pc.sweeps.size() * sizeof(TileSweep)), pc.recs.data(),
+                pc.recs.size());
 }
 
 static int launch_pass(sv_state *h, const PassCode &pc, size_t off) {
     const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + off);
-    const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + off +
-                                                            align256(pc.sweeps.size() * sizeof(TileSweep)));
+    const char *gt = h->d_arena + off + align256(pc.sweeps.size() * sizeof(TileSweep));
     Timed tm(h, K_TILE, 2.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
     SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, pc.two_qubit, pc.direct,
                        h->stream));
@@ -1168,7 +1256,8 @@ struct BatchProgram {
     std::vector<BatchCircuit> circuits;
     std::vector<BatchPass> passes;
     std::vector<TileSweep> sweeps;
-    std::vector<TileGate> gates;
+    std::vector<char> recs; // packed records of all passes
+    bool two_qubit = false;
     std::vector<int32_t> order;
     size_t state_bytes = 0;
 };
@@ -1223,10 +1312,11 @@ static BatchProgram compile_batch(const std::vector<int> &widths,
             q.sp = sp;
             q.n_sweeps = (int)pc.sweeps.size();
             q.sweep_off = (int)bp.sweeps.size();
-            q.gate_off = (int)bp.gates.size();
+            q.gate_off = (int)bp.recs.size();
             bp.passes.push_back(q);
             bp.sweeps.insert(bp.sweeps.end(), pc.sweeps.begin(), pc.sweeps.end());
-            bp.gates.insert(bp.gates.end(), pc.gates.begin(), pc.gates.end());
+            bp.recs.insert(bp.recs.end(), pc.recs.begin(), pc.recs.end());
+            bp.two_qubit = bp.two_qubit || pc.two_qubit;
         }
         bp.circuits.push_back(c);
         cost[i] = std::ldexp((double)(circ[i].size() + 1) * (double)passes.size(), w);
@@ -1284,7 +1374,7 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
     const size_t o_p = align256(o_c + bp.circuits.size() * sizeof(BatchCircuit));
     const size_t o_s = align256(o_p + bp.passes.size() * sizeof(BatchPass));
     const size_t o_g = align256(o_s + bp.sweeps.size() * sizeof(TileSweep));
-    const size_t o_o = align256(o_g + bp.gates.size() * sizeof(TileGate));
+    const size_t o_o = align256(o_g + bp.recs.size());
     const size_t total = align256(o_o + bp.order.size() * sizeof(int32_t));
     size_t free_b = 0, total_b = 0;
     SV_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -1296,14 +1386,14 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
     std::memcpy(host.data() + o_c, bp.circuits.data(), bp.circuits.size() * sizeof(BatchCircuit));
     std::memcpy(host.data() + o_p, bp.passes.data(), bp.passes.size() * sizeof(BatchPass));
     std::memcpy(host.data() + o_s, bp.sweeps.data(), bp.sweeps.size() * sizeof(TileSweep));
-    std::memcpy(host.data() + o_g, bp.gates.data(), bp.gates.size() * sizeof(TileGate));
+    std::memcpy(host.data() + o_g, bp.recs.data(), bp.recs.size());
     std::memcpy(host.data() + o_o, bp.order.data(), bp.order.size() * sizeof(int32_t));
     SV_HIP(hipMemcpy(b->d_prog, host.data(), total, hipMemcpyHostToDevice));
     BatchArgs &a = b->args;
     a.circuits = reinterpret_cast<const BatchCircuit *>(b->d_prog + o_c);
     a.passes = reinterpret_cast<const BatchPass *>(b->d_prog + o_p);
     a.sweeps = reinterpret_cast<const TileSweep *>(b->d_prog + o_s);
-    a.gates = reinterpret_cast<const TileGate *>(b->d_prog + o_g);
+    a.recs = b->d_prog + o_g;
     a.order = reinterpret_cast<const int32_t *>(b->d_prog + o_o);
     a.counter = b->d_counter;
     a.states = b->d_states;
@@ -1319,7 +1409,7 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
     b->tile_m = tile_m;
     b->sweep_w = sweep_w;
     b->grid = grid;
-    b->two_qubit = std::any_of(bp.gates.begin(), bp.gates.end(), [](const TileGate &r) { return r.kind == SK_2Q; });
+    b->two_qubit = bp.two_qubit;
     // one eager launch (sets kernel attributes, checks the launch), then capture
     SV_HIP(launch_batch(a, b->dtype, sweep_w, tile_m, grid, b->two_qubit, b->stream));
     SV_HIP(hipStreamSynchronize(b->stream));
@@ -1898,8 +1988,7 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops, con
     for (size_t pi = 0; pi < split.size(); ++pi) {
         const PassCode &pc = code[pi];
         const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + offs[pi]);
-        const TileGate *gt = reinterpret_cast<const TileGate *>(h->d_arena + offs[pi] +
-                                                                align256(pc.sweeps.size() * sizeof(TileSweep)));
+        const char *gt = h->d_arena + offs[pi] + align256(pc.sweeps.size() * sizeof(TileSweep));
         Timed tm(h, K_ADJOINT, 4.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
         hipError_t e = launch_adjoint_tile(h->amps, lam->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt,
                                            slot0[pi], nslot[pi], partials + loss_n, B, pc.two_qubit, h->stream);

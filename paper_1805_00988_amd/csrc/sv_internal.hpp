@@ -82,8 +82,15 @@ enum SweepKind : int32_t {
     SK_PARAM = 6, // adjoint sweep: add Im<lam|M|psi> for M (entries 0-3) on position b0
                   // to slot b1; the undo of the gate follows as its own record
     SK_DIAGR = 7, // diag(d0, d1) on sweep position b0; m: d0, d1
-    SK_RIMAG = 8  // 2x2 on sweep position b0 with real diagonal and imaginary
+    SK_RIMAG = 8, // 2x2 on sweep position b0 with real diagonal and imaginary
                   // off-diagonal entries (RX, Y); m: the four complex entries
+    SK_PHASE = 9, // phase m[0] on the amplitudes with all bits of the record's
+                  // condition set, gathered into a per-lane factor: slot b0 =
+                  // sweep position p (the condition's one register bit) or W
+                  // (none); amask 1
+    SK_FLUSH = 10 // multiply every amplitude by its gathered factors (slot W for
+                  // all, slot p for those with register bit p) and reset the
+                  // slots in amask
 };
 // Controls inside the tile are split by where they sit in the sweep: bits
 // on tile positions outside the registers ('lane') are constant over one
@@ -92,22 +99,29 @@ enum SweepKind : int32_t {
 // 'amask': bit j is set for every register index j the record starts an
 // update at (the low index of each pair or quad whose controls hold; for a
 // diagonal gate every amplitude whose factor can differ from 1).
+// On the device the records of a pass form one packed byte stream: each is
+// this layout cut after the matrix entries its kind reads (record_entries),
+// 'size' bytes long, so that a pass's records stay in the scalar data cache
+// while every wave walks them; the stream ends with kRecordTail zero bytes
+// (the record head is read as one 96-byte block).
 struct TileGate {
     int32_t kind;
     int32_t b0, b1;
     uint32_t lane;     // control bits on tile positions outside the registers
     uint32_t amask;    // register indices updated (see above)
-    uint32_t pad;
+    int32_t size;      // bytes of the packed record
     uint64_t cout;     // control bits outside the tile (global positions)
     double m[32];      // matrix entries, complex interleaved: FP64, or FP32 packed into
                        // the first half of the storage for complex64 states
 };
+constexpr int kRecordHead = 32, kRecordTail = 96;
 
 constexpr int kSweepW = 4; // tile qubits held in registers per sweep (fewer for tiny tiles)
 struct TileSweep {
-    int32_t n_gates;       // gates of this sweep, stored consecutively
+    int32_t n_gates;       // records of this sweep, stored consecutively
     int32_t qpos[kSweepW]; // ascending local positions held in registers
-    int32_t pad[3];
+    int32_t rec_off;       // byte offset of its first record in the pass's stream
+    int32_t pad[2];
 };
 
 // LDS swizzle of a tile index, linear over XOR (and its own inverse): the
@@ -148,7 +162,7 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
 // wave's accesses stay contiguous).
 constexpr uint32_t kDirectFirst = 1, kDirectLast = 2;
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const TileGate *dev_gates, bool two_qubit, uint32_t direct,
+                       int n_sweeps, const char *dev_recs, bool two_qubit, uint32_t direct,
                        hipStream_t s);
 int tile_max_qubits(int dtype);
 int batch_tile_qubits(int dtype);
@@ -207,14 +221,14 @@ struct BatchPass {
     TileSpec sp;
     int32_t n_sweeps;
     int32_t sweep_off;
-    int32_t gate_off;
+    int32_t gate_off;      // byte offset of the pass's records in the stream
     int32_t pad;
 };
 struct BatchArgs {
     const BatchCircuit *circuits;
     const BatchPass *passes;
     const TileSweep *sweeps;
-    const TileGate *gates;
+    const char *recs;
     const int32_t *order;
     unsigned int *counter;
     void *states;
@@ -257,7 +271,7 @@ hipError_t launch_sum_slots(const double *partials, int n_slots, int n_blocks, d
 // Probes of the pass's parametrised gates accumulate per workgroup and are
 // written to partials[(slot0 + i) * n_blocks + workgroup] for i < n_slots.
 hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,
-                               const TileSweep *dev_sweeps, int n_sweeps, const TileGate *dev_gates,
+                               const TileSweep *dev_sweeps, int n_sweeps, const char *dev_recs,
                                int slot0, int n_slots, double *partials, int n_blocks, bool two_qubit,
                                hipStream_t s);
 int adjoint_tile_qubits(int dtype);

@@ -253,6 +253,13 @@ __device__ __forceinline__ void rswap(cpx<double> &a, cpx<double> &b, uint32_t a
                 "v_mov_b64 %3, %5",
                 SV_OUTS("+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im), "=&v"(t0), "=&v"(t1)));
 }
+// x <- 1, in place
+__device__ __forceinline__ void rone(cpx<float> &x) {
+    asm volatile("v_mov_b32 %0, 1.0\n\tv_mov_b32 %1, 0" : "+v"(x.re), "+v"(x.im));
+}
+__device__ __forceinline__ void rone(cpx<double> &x) {
+    asm volatile("v_mov_b64 %0, 1.0\n\tv_mov_b64 %1, 0" : "+v"(x.re), "+v"(x.im));
+}
 #undef SV_OUTS
 #undef SV_INS
 #undef SV_ASM
@@ -387,6 +394,58 @@ __device__ __forceinline__ void sweep_diag_lane(cpx<T> (&v)[1 << W], uint32_t gb
 }
 #undef SV_J
 
+// Phase factors gathered per lane (SK_PHASE) until a flush applies them:
+// f[W] multiplies every amplitude of the group, f[p] those with register
+// bit p set.
+template <typename T, int W>
+struct PhaseAcc {
+    cpx<T> f[W + 1];
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int s = 0; s <= W; ++s) f[s] = cpx<T>{T(1), T(0)};
+    }
+};
+
+template <typename T, int W, int S = 0>
+__device__ __forceinline__ void phase_gather(PhaseAcc<T, W> &acc, int slot, cpx<T> d) {
+    if constexpr (S == W) {
+        rmul<0, false>(acc.f[W], d, 0u);
+    } else {
+        if (slot == S) rmul<0, false>(acc.f[S], d, 0u);
+        else phase_gather<T, W, S + 1>(acc, slot, d);
+    }
+}
+
+// v[j] *= f[p] for the register indices j with bit p set, p = B .. W-1,
+// where slot p is in 'used'
+template <typename T, int W, int B = 0>
+__device__ __forceinline__ void phase_flush_bits(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t used) {
+    if constexpr (B < W) {
+        // enable mask: every register index when the slot is used, else none
+        const uint32_t on = __builtin_amdgcn_readfirstlane((used >> B) & 1u ? 0xffffffffu : 0u);
+        constexpr uint32_t UP = index_set<W>(0) & ~index_set<W>(1u << B);
+        for_each_index<UP, (1 << W)>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            rmul<j, true>(v[j], acc.f[B], on);
+        });
+        phase_flush_bits<T, W, B + 1>(v, acc, used);
+    }
+}
+
+// v[j] *= f[W] * prod_{p in j} f[p] over the slots in 'used'; every slot is
+// reset to 1.
+template <typename T, int W>
+__device__ __forceinline__ void phase_flush(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t used) {
+    const uint32_t all = __builtin_amdgcn_readfirstlane((used >> W) & 1u ? 0xffffffffu : 0u);
+    for_each_index<index_set<W>(0), (1 << W)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        rmul<j, true>(v[j], acc.f[W], all);
+    });
+    phase_flush_bits<T, W>(v, acc, used);
+#pragma unroll
+    for (int s = 0; s <= W; ++s) rone(acc.f[s]);
+}
+
 // Apply one record to a group held in registers; gb holds the group's own
 // tile bits, base is the global index of the tile's amplitude 0 (the
 // record's controls outside the tile hold for the whole tile or not at all:
@@ -397,12 +456,18 @@ __device__ __forceinline__ void sweep_diag_lane(cpx<T> (&v)[1 << W], uint32_t gb
 // are rewritten, keep the compiler from holding the group in place across
 // the dispatch, so passes without them use kernels without that path.
 template <typename T, int W, bool TWOQ>
-__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], uint32_t gb, const TileGate &G, uint64_t base) {
+__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
+                                             const TileGate &G, uint64_t base) {
     const GateHot h = *reinterpret_cast<const GateHot *>(&G);
     const int kind = h.kind;
     const bool ok = (gb & h.lane) == h.lane;
     const uint32_t am = __builtin_amdgcn_readfirstlane((base & h.cout) == h.cout ? h.amask : 0u);
-    if (kind == SK_DIAG) {
+    if (kind == SK_PHASE) {
+        const cpx<T> d = ok && am != 0u ? hmat<T>(h, 0) : cpx<T>{T(1), T(0)};
+        phase_gather<T, W>(acc, h.b0, d);
+    } else if (kind == SK_FLUSH) {
+        phase_flush<T, W>(v, acc, am);
+    } else if (kind == SK_DIAG) {
         sweep_diag_lane<T, W>(v, gb, ok, h, am);
     } else if (TWOQ && W >= 2 && kind == SK_2Q) {
         if constexpr (TWOQ && W >= 2) {
@@ -475,13 +540,13 @@ __device__ __forceinline__ void register_offsets(const TileSweep &S, uint32_t (&
 // lds_phys(gb) ^ lds_phys(register bits of j).
 template <typename T, int W, bool TWOQ>
 __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSweep *__restrict__ sweeps,
-                                int n_sweeps, const TileGate *__restrict__ gates) {
+                                int n_sweeps, const char *__restrict__ recs) {
     constexpr int D = 1 << W;
     const uint32_t n_groups = (1u << m) >> W;
-    int goff = 0;
     for (int si = 0; si < n_sweeps; ++si) {
         const TileSweep &S = sweeps[si];
         const int ng = S.n_gates;
+        const char *r0 = recs + S.rec_off;
         uint32_t PF[D];
         register_offsets<T, W>(S, PF);
         for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
@@ -494,14 +559,17 @@ __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSwe
                 addr[j] = pg ^ PF[j];
                 v[j] = lds[addr[j]];
             }
+            PhaseAcc<T, W> acc;
+            acc.init();
+            const char *rp = r0;
             for (int gi = 0; gi < ng; ++gi) {
-                const TileGate &G = gates[goff + gi];
-                sweep_gate_t<T, W, TWOQ>(v, gb, G, base);
+                const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
+                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+                rp += G.size;
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) lds[addr[j]] = v[j];
         }
-        goff += ng;
         __syncthreads();
     }
 }

@@ -117,6 +117,38 @@ def test_diagonal_and_phase_gates(dtype):
         assert_state_close(got, ref, dtype, len(gates))
 
 
+def phase_run_circuit(n, n_phase, seed):
+    """Hadamards on every qubit, then runs of phase gates (U1, Z, S, T with
+    0-2 controls on random qubits, so that their conditions fall on register
+    positions, lane bits and qubits outside the tile), broken by an RZ or an
+    RX now and then (runs of 1 to 12 gates), then Hadamards again."""
+    rng = np.random.default_rng(seed)
+    gates = [C.Gate("H", (q,)) for q in range(n)]
+    left = n_phase
+    while left > 0:
+        run = int(min(left, rng.integers(1, 13)))
+        for _ in range(run):
+            qs = rng.choice(n, size=1 + int(rng.integers(0, 3)), replace=False)
+            name = ["U1", "Z", "S", "T"][int(rng.integers(0, 4))]
+            theta = float(rng.uniform(0, 6.28)) if name == "U1" else None
+            gates.append(C.Gate(name, (int(qs[0]),), tuple(int(q) for q in qs[1:]), theta))
+        left -= run
+        t = int(rng.integers(0, n))
+        gates.append(C.Gate(["RZ", "RX"][int(rng.integers(0, 2))], (t,), (), float(rng.uniform(0, 6.28))))
+    gates += [C.Gate("H", (q,)) for q in range(n)]
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [5, 14, 17])
+def test_phase_runs_tiled(dtype, n):
+    """Runs of commuting phase gates, gathered into per-lane factors by the
+    tile pass, against the oracle's gate-by-gate application."""
+    gates = phase_run_circuit(n, 160, seed=20 + n)
+    got, ref = run_both(n, dtype, gates, seed=21, mode=sv.SV_RUN_TILED)
+    assert_state_close(got, ref, dtype, len(gates))
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("mode", ["per_gate", "tiled"])
 def test_config0_random_circuit(dtype, mode):
