@@ -305,13 +305,14 @@ struct PassCode {
     size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + recs.size(); }
 };
 
-// Complex matrix entries a record kind reads on the device.
-static int record_entries(int kind) {
-    switch (kind) {
-    case SK_2Q: return 16;
-    case SK_GEN: case SK_REAL: case SK_RIMAG: case SK_PARAM: return 4;
-    case SK_DIAG: case SK_DIAGR: return 2;
-    case SK_PHASE: return 1;
+// Bytes of matrix data a record reads on the device.
+static size_t record_payload(const TileGate &r, bool f32) {
+    const size_t c = f32 ? 8 : 16; // one complex entry
+    switch (r.kind) {
+    case SK_2Q: return 16 * c;
+    case SK_GEN: case SK_REAL: case SK_RIMAG: case SK_PARAM: return 4 * c;
+    case SK_DIAG: case SK_DIAGR: return 2 * c;
+    case SK_PHASE: return (size_t)r.b1 * (8 + c); // b1 entries of (condition, phase)
     default: return 0; // SK_SWAP, SK_FLUSH
     }
 }
@@ -325,7 +326,7 @@ static void pack_records(PassCode &pc, bool f32) {
         S.rec_off = (int32_t)pc.recs.size();
         for (int k = 0; k < S.n_gates; ++k, ++gi) {
             TileGate r = pc.gates[gi];
-            const size_t sz = ((size_t)kRecordHead + (size_t)record_entries(r.kind) * (f32 ? 8 : 16) + 7) & ~(size_t)7;
+            const size_t sz = ((size_t)kRecordHead + record_payload(r, f32) + 7) & ~(size_t)7;
             r.size = (int32_t)sz;
             const char *src = reinterpret_cast<const char *>(&r);
             pc.recs.insert(pc.recs.end(), src, src + sz);
@@ -543,9 +544,42 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
                 a = b == a ? a + 1 : b;
             }
         }
+        // A gathered run emits one record per (slot, per-lane mask) with the
+        // list of its gates' outside-tile conditions and phases (the factor
+        // of the tile is the product of the phases whose condition holds),
+        // then a flush.
         uint32_t pending = 0;
+        std::vector<std::pair<std::pair<int, uint32_t>, std::vector<std::pair<uint64_t, const double *>>>> groups;
+        const size_t entry_bytes = 8 + (f32 ? 8 : 16);
+        const int max_entries = (int)(sizeof(TileGate::m) / entry_bytes);
         auto flush = [&]() {
             if (!pending) return;
+            for (const auto &grp : groups) {
+                const auto &ents = grp.second;
+                for (size_t e0 = 0; e0 < ents.size(); e0 += (size_t)max_entries) {
+                    TileGate r{};
+                    r.kind = SK_PHASE;
+                    r.b0 = grp.first.first;
+                    r.lane = grp.first.second;
+                    r.amask = 1;
+                    const size_t ne = std::min(ents.size() - e0, (size_t)max_entries);
+                    r.b1 = (int32_t)ne;
+                    char *dst = reinterpret_cast<char *>(r.m);
+                    for (size_t e = 0; e < ne; ++e, dst += entry_bytes) {
+                        std::memcpy(dst, &ents[e0 + e].first, 8);
+                        const double *ph = ents[e0 + e].second;
+                        if (f32) {
+                            const float f[2] = {(float)ph[0], (float)ph[1]};
+                            std::memcpy(dst + 8, f, 8);
+                        } else {
+                            std::memcpy(dst + 8, ph, 16);
+                        }
+                    }
+                    pc.gates.push_back(r);
+                    ++sw.n_gates;
+                }
+            }
+            groups.clear();
             TileGate r{};
             r.kind = SK_FLUSH;
             r.amask = pending;
@@ -559,13 +593,13 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
                 const Gate &g = *gs[i];
                 TileGate r{};
                 const uint32_t cond = encode_controls(sp, g.ctrl, &r) | (1u << local_bit(sp, g.t[0]));
-                r.kind = SK_PHASE;
-                r.b0 = slot[ci];
-                r.lane = cond & ~fall;
-                r.amask = 1;
-                put_matrix(r, g.U + 6, 1, f32);
-                pc.gates.push_back(r);
-                ++sw.n_gates;
+                const std::pair<int, uint32_t> key{slot[ci], cond & ~fall};
+                auto it = std::find_if(groups.begin(), groups.end(), [&](const auto &x) { return x.first == key; });
+                if (it == groups.end()) {
+                    groups.push_back({key, {}});
+                    it = groups.end() - 1;
+                }
+                it->second.push_back({r.cout, g.U + 6});
                 pending |= 1u << slot[ci];
                 pc.flops_per_amp += gate_flops_per_amp(g);
                 continue;

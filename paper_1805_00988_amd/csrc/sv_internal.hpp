@@ -84,10 +84,12 @@ enum SweepKind : int32_t {
     SK_DIAGR = 7, // diag(d0, d1) on sweep position b0; m: d0, d1
     SK_RIMAG = 8, // 2x2 on sweep position b0 with real diagonal and imaginary
                   // off-diagonal entries (RX, Y); m: the four complex entries
-    SK_PHASE = 9, // phase m[0] on the amplitudes with all bits of the record's
-                  // condition set, gathered into a per-lane factor: slot b0 =
-                  // sweep position p (the condition's one register bit) or W
-                  // (none); amask 1
+    SK_PHASE = 9, // b1 phases gathered into a per-lane factor: the record's
+                  // entries are (uint64 condition outside the tile, complex phase);
+                  // the product of the phases whose condition holds for the tile
+                  // multiplies slot b0 (sweep position p: the amplitudes with
+                  // register bit p set, or W: all) in lanes whose group holds
+                  // 'lane'; amask 1
     SK_FLUSH = 10 // multiply every amplitude by its gathered factors (slot W for
                   // all, slot p for those with register bit p) and reset the
                   // slots in amask

@@ -463,8 +463,14 @@ __device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
     const bool ok = (gb & h.lane) == h.lane;
     const uint32_t am = __builtin_amdgcn_readfirstlane((base & h.cout) == h.cout ? h.amask : 0u);
     if (kind == SK_PHASE) {
-        const cpx<T> d = ok && am != 0u ? hmat<T>(h, 0) : cpx<T>{T(1), T(0)};
-        phase_gather<T, W>(acc, h.b0, d);
+        // tile factor: product of the entries' phases whose condition holds
+        const char *e = reinterpret_cast<const char *>(&G) + kRecordHead;
+        cpx<T> u{T(1), T(0)};
+        for (int i = 0; i < h.b1; ++i, e += 8 + sizeof(cpx<T>)) {
+            const uint64_t c = *reinterpret_cast<const uint64_t *>(e);
+            if ((base & c) == c) u = cmul(u, *reinterpret_cast<const cpx<T> *>(e + 8));
+        }
+        phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
     } else if (kind == SK_FLUSH) {
         phase_flush<T, W>(v, acc, am);
     } else if (kind == SK_DIAG) {
