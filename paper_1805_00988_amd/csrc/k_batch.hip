@@ -53,9 +53,87 @@ __device__ __forceinline__ double zterm(cpx<T> a, uint64_t x, uint64_t zmask) {
     return (__popcll(x & zmask) & 1) ? -p : p;
 }
 
+// One pass of a circuit over one tile.  As in the gate tile pass, the first
+// sweep takes its register groups straight from the source and the last
+// hands them straight to the sink, so the tile crosses LDS only between
+// sweeps: the source is |0...0> synthesised in registers on the circuit's
+// first pass, else the state; the sink accumulates the Z-string terms on
+// the last pass and stores the state unless that pass is the last and the
+// states are not kept.  A thread owns at most one group per sweep
+// (2^(m-W) <= kBatchThreads).
+template <typename T, int W, bool TWOQ>
+__device__ void batch_tile(cpx<T> *state, cpx<T> *lds, const TileSpec &sp, int m, uint64_t base,
+                           const TileSweep *__restrict__ sweeps, int n_sweeps, const char *__restrict__ recs,
+                           bool synth, bool last_pass, bool store, uint64_t zmask, double &zacc) {
+    constexpr int D = 1 << W;
+    const uint32_t n_groups = (1u << m) >> W;
+    for (int si = 0; si < n_sweeps; ++si) {
+        const TileSweep &S = sweeps[si];
+        const bool first = si == 0, last = si == n_sweeps - 1;
+        uint32_t pb[W];
+        uint64_t gbit[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            pb[b] = lds_phys<T>(1u << S.qpos[b]);
+            gbit[b] = tile_offset(sp, 1u << S.qpos[b]);
+        }
+        auto goff_of = [&](int j) {
+            uint64_t o = 0;
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+                if ((j >> b) & 1) o |= gbit[b];
+            return o;
+        };
+        auto poff_of = [&](int j) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+                if ((j >> b) & 1) o ^= pb[b];
+            return o;
+        };
+        for (uint32_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
+            const uint32_t gb = group_bits<W>(S, g);
+            const uint32_t pg = lds_phys<T>(gb);
+            const uint64_t row = base | tile_offset(sp, gb);
+            cpx<T> v[D];
+            if (first && synth) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = cpx<T>{(row | goff_of(j)) == 0 ? T(1) : T(0), T(0)};
+            } else if (first) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = state[row | goff_of(j)];
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = lds[pg ^ poff_of(j)];
+            }
+            PhaseAcc<T, W> acc;
+            acc.init();
+            const char *rp = recs + S.rec_off;
+            for (int gi = 0; gi < S.n_gates; ++gi) {
+                const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
+                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+                rp += G.size;
+            }
+            if (last) {
+                if (last_pass) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) zacc += zterm(v[j], row | goff_of(j), zmask);
+                }
+                if (store) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) state[row | goff_of(j)] = v[j];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j) lds[pg ^ poff_of(j)] = v[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int W, bool TWOQ>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
-    using V = BV<T>;
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
     __shared__ int s_idx;
@@ -68,55 +146,18 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
         if (qi >= a.n_circuits) break; // uniform: every wave leaves together
         const int ci = a.order[qi];
         const BatchCircuit &c = a.circuits[ci]; // read through memory (uniform)
-        typename V::type *state = reinterpret_cast<typename V::type *>(
-            reinterpret_cast<char *>(a.states) + c.state_off);
+        cpx<T> *state = reinterpret_cast<cpx<T> *>(reinterpret_cast<char *>(a.states) + c.state_off);
         double zacc = 0.0;
         for (int pi = 0; pi < c.n_passes; ++pi) {
             const BatchPass &p = a.passes[c.pass_off + pi];
             const int m = p.sp.L + p.sp.K;
-            const uint32_t tsize = 1u << m, tvec = tsize >> V::bits;
             const uint64_t n_tiles = 1ull << (c.w - m);
             const bool last = pi == c.n_passes - 1;
             for (uint64_t tile = 0; tile < n_tiles; ++tile) {
                 uint64_t base = tile << p.sp.L;
                 for (int i = 0; i < p.sp.K; ++i) base = insert_zero(base, p.sp.high[i]);
-                if (pi == 0) {
-                    for (uint32_t l = threadIdx.x; l < tsize; l += kBatchThreads)
-                        lds[lds_phys<T>(l)] = cpx<T>{(base == 0 && l == 0) ? T(1) : T(0), T(0)};
-                } else {
-                    for (uint32_t l = threadIdx.x; l < tvec; l += kBatchThreads) {
-                        const uint32_t la = l << V::bits;
-                        const typename V::type w = state[btile_addr(p.sp, base, la) >> V::bits];
-                        if constexpr (V::bits == 1) {
-                            lds[lds_phys<T>(la)] = cpx<T>{w.x, w.y};
-                            lds[lds_phys<T>(la + 1)] = cpx<T>{w.z, w.w};
-                        } else {
-                            lds[lds_phys<T>(la)] = cpx<T>{w.x, w.y};
-                        }
-                    }
-                }
-                __syncthreads();
-                tile_run_sweeps<T, W, TWOQ>(lds, m, base, a.sweeps + p.sweep_off, p.n_sweeps,
-                                      a.recs + p.gate_off);
-                if (last) {
-                    for (uint32_t l = threadIdx.x; l < tsize; l += kBatchThreads)
-                        zacc += zterm(lds[lds_phys<T>(l)], btile_addr(p.sp, base, l), a.zmask);
-                }
-                if (!last || c.keep) {
-                    for (uint32_t l = threadIdx.x; l < tvec; l += kBatchThreads) {
-                        const uint32_t la = l << V::bits;
-                        typename V::type w;
-                        if constexpr (V::bits == 1) {
-                            const cpx<T> u0 = lds[lds_phys<T>(la)], u1 = lds[lds_phys<T>(la + 1)];
-                            w = float4{u0.re, u0.im, u1.re, u1.im};
-                        } else {
-                            const cpx<T> u0 = lds[lds_phys<T>(la)];
-                            w = double2{u0.re, u0.im};
-                        }
-                        state[btile_addr(p.sp, base, la) >> V::bits] = w;
-                    }
-                }
-                __syncthreads();
+                batch_tile<T, W, TWOQ>(state, lds, p.sp, m, base, a.sweeps + p.sweep_off, p.n_sweeps,
+                                       a.recs + p.gate_off, pi == 0, last, !last || c.keep, a.zmask, zacc);
             }
             // the next pass reads what this pass wrote: make the stores visible
             __threadfence();

@@ -1341,7 +1341,16 @@ static BatchProgram compile_batch(const std::vector<int> &widths,
             } else {
                 tile_layout(w, m, lmin, needed, &sp);
             }
-            const PassCode pc = compile_pass(sp, ptrs, sweep_w, dtype == SV_C64);
+            PassCode pc = compile_pass(sp, ptrs, sweep_w, dtype == SV_C64);
+            if (pc.sweeps.empty()) {
+                // a circuit without gates still needs one sweep: the batch
+                // kernel synthesises |0...0> and reduces in a sweep's registers
+                TileSweep sw{};
+                const int W = std::min(pc.m, sweep_w);
+                for (int b = 0; b < W; ++b) sw.qpos[b] = pc.m - W + b;
+                sw.rec_off = 0;
+                pc.sweeps.push_back(sw);
+            }
             BatchPass q{};
             q.sp = sp;
             q.n_sweeps = (int)pc.sweeps.size();

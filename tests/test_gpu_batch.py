@@ -71,6 +71,32 @@ def test_batch_states_and_expectations(dtype):
     b.close()
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_gateless_and_diagonal_circuits(dtype):
+    """Circuits without gates (|0...0>, <Z_0> = 1) and circuits of phase
+    gates only, one tile wide and wider than a tile, mixed with ordinary
+    ones: the first sweep synthesises |0...0> in registers and the last
+    reduces from registers."""
+    circs = []
+    for w in (5, 13, 15):
+        circs.append(C.Circuit(w, [], 0, None, f"empty_{w}"))
+        gates = [C.Gate("H", (q,)) for q in range(w)]
+        gates += [C.Gate("U1", (q,), ((q + 1) % w,), 0.3 + 0.1 * q) for q in range(w)]
+        gates += [C.Gate("Z", (q,)) for q in range(0, w, 2)]
+        circs.append(C.Circuit(w, gates, 0, None, f"phases_{w}"))
+    circs += mixed_circuits(dtype, 6, seed=7)
+    b = sv.Batch(circs, dtype, z_mask=1, keep_states=True)
+    b.run()
+    z = b.results()
+    for i, c in enumerate(circs):
+        ref = O.run(c)
+        got = b.state(i).astype(np.complex128)
+        tol = C128_ATOL if dtype == "c128" else c64_bound(max(1, len(c)))
+        assert np.max(np.abs(got - ref)) <= tol, (i, c.n)
+        assert abs(z[i] - z_of(ref, c.n, 1)) <= 2 * tol, (i, c.n)
+    b.close()
+
+
 def test_batch_autotuner_keeps_results():
     circs = mixed_circuits("c64", 64, seed=2)
     b = sv.Batch(circs, "c64", z_mask=0b101)
