@@ -417,33 +417,35 @@ __device__ __forceinline__ void phase_gather(PhaseAcc<T, W> &acc, int slot, cpx<
 }
 
 // v[j] *= f[p] for the register indices j with bit p set, p = B .. W-1,
-// where slot p is in 'used'
+// where slot p is in 'used' (one uniform branch per slot around untested
+// updates)
 template <typename T, int W, int B = 0>
 __device__ __forceinline__ void phase_flush_bits(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t used) {
     if constexpr (B < W) {
-        // enable mask: every register index when the slot is used, else none
-        const uint32_t on = __builtin_amdgcn_readfirstlane((used >> B) & 1u ? 0xffffffffu : 0u);
         constexpr uint32_t UP = index_set<W>(0) & ~index_set<W>(1u << B);
-        for_each_index<UP, (1 << W)>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            rmul<j, true>(v[j], acc.f[B], on);
-        });
+        if ((used >> B) & 1u) {
+            for_each_index<UP, (1 << W)>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                rmul<j, false>(v[j], acc.f[B], 0u);
+            });
+            rone(acc.f[B]);
+        }
         phase_flush_bits<T, W, B + 1>(v, acc, used);
     }
 }
 
-// v[j] *= f[W] * prod_{p in j} f[p] over the slots in 'used'; every slot is
-// reset to 1.
+// v[j] *= f[W] * prod_{p in j} f[p] over the slots in 'used'; the used
+// slots are reset to 1.
 template <typename T, int W>
 __device__ __forceinline__ void phase_flush(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t used) {
-    const uint32_t all = __builtin_amdgcn_readfirstlane((used >> W) & 1u ? 0xffffffffu : 0u);
-    for_each_index<index_set<W>(0), (1 << W)>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        rmul<j, true>(v[j], acc.f[W], all);
-    });
+    if ((used >> W) & 1u) {
+        for_each_index<index_set<W>(0), (1 << W)>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            rmul<j, false>(v[j], acc.f[W], 0u);
+        });
+        rone(acc.f[W]);
+    }
     phase_flush_bits<T, W>(v, acc, used);
-#pragma unroll
-    for (int s = 0; s <= W; ++s) rone(acc.f[s]);
 }
 
 // Apply one record to a group held in registers; gb holds the group's own
@@ -466,9 +468,15 @@ __device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
         // tile factor: product of the entries' phases whose condition holds
         const char *e = reinterpret_cast<const char *>(&G) + kRecordHead;
         cpx<T> u{T(1), T(0)};
-        for (int i = 0; i < h.b1; ++i, e += 8 + sizeof(cpx<T>)) {
-            const uint64_t c = *reinterpret_cast<const uint64_t *>(e);
-            if ((base & c) == c) u = cmul(u, *reinterpret_cast<const cpx<T> *>(e + 8));
+        // the entry's phase or 1, chosen on the scalar unit: no branch, so
+        // the loads of consecutive entries issue together
+#pragma unroll 4
+        for (int i = 0; i < h.b1; ++i) {
+            const char *ei = e + (size_t)i * (8 + sizeof(cpx<T>));
+            const uint64_t c = *reinterpret_cast<const uint64_t *>(ei);
+            const cpx<T> ph = *reinterpret_cast<const cpx<T> *>(ei + 8);
+            const bool on = (base & c) == c;
+            u = cmul(u, cpx<T>{on ? ph.re : T(1), on ? ph.im : T(0)});
         }
         phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
     } else if (kind == SK_FLUSH) {
