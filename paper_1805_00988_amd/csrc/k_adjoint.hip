@@ -182,17 +182,32 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
     __shared__ double slot_acc[kMaxAdjSlots];
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) slot_acc[i] = 0.0;
     const uint32_t n_groups = tsize >> W;
+    cpx<T> *ps = reinterpret_cast<cpx<T> *>(psi);
+    cpx<T> *ls = reinterpret_cast<cpx<T> *>(lam);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        tile_load<T, kAdjThreads, 4>(psi, lp, sp, base, tsize);
-        tile_load<T, kAdjThreads, 4>(lam, ll, sp, base, tsize);
-        __syncthreads();
+        // the first sweep reads both vectors' register groups straight from
+        // HBM and the last writes them straight back; only the sweeps in
+        // between exchange the tiles through LDS (each sweep ends with a
+        // barrier, which also orders this tile's last LDS reads before the
+        // next tile's first LDS writes)
         for (int si = 0; si < n_sweeps; ++si) {
             const TileSweep &S = sweeps[si];
             const int ng = S.n_gates;
+            const bool first = si == 0, last = si == n_sweeps - 1;
             uint32_t PF[D];
             register_offsets<T, W>(S, PF);
+            uint64_t gbit[W];
+#pragma unroll
+            for (int b = 0; b < W; ++b) gbit[b] = tile_offset(sp, 1u << S.qpos[b]);
+            auto goff_of = [&](int j) {
+                uint64_t o = 0;
+#pragma unroll
+                for (int b = 0; b < W; ++b)
+                    if ((j >> b) & 1) o |= gbit[b];
+                return o;
+            };
             // every lane runs the same number of iterations (the probe's wave
             // reduction needs all 64 lanes); lanes past the last group add 0
             for (uint32_t g0 = 0; g0 < n_groups; g0 += blockDim.x) {
@@ -200,13 +215,22 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                 const bool act = g < n_groups;
                 const uint32_t gb = group_bits<W>(S, act ? g : 0u);
                 const uint32_t pg = lds_phys<T>(gb);
+                const uint64_t row = base | tile_offset(sp, gb);
                 cpx<T> v[D], w[D];
                 PhaseAcc<T, W> acc_unused;
                 acc_unused.init();
+                if (first) {
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    v[j] = lp[pg ^ PF[j]];
-                    w[j] = ll[pg ^ PF[j]];
+                    for (int j = 0; j < D; ++j) {
+                        v[j] = act ? ps[row | goff_of(j)] : cpx<T>{T(0), T(0)};
+                        w[j] = act ? ls[row | goff_of(j)] : cpx<T>{T(0), T(0)};
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        v[j] = lp[pg ^ PF[j]];
+                        w[j] = ll[pg ^ PF[j]];
+                    }
                 }
                 const char *rp = recs + S.rec_off;
                 for (int gi = 0; gi < ng; ++gi) {
@@ -225,18 +249,23 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                     }
                 }
                 if (act) {
+                    if (last) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        lp[pg ^ PF[j]] = v[j];
-                        ll[pg ^ PF[j]] = w[j];
+                        for (int j = 0; j < D; ++j) {
+                            ps[row | goff_of(j)] = v[j];
+                            ls[row | goff_of(j)] = w[j];
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < D; ++j) {
+                            lp[pg ^ PF[j]] = v[j];
+                            ll[pg ^ PF[j]] = w[j];
+                        }
                     }
                 }
             }
             __syncthreads();
         }
-        tile_store<T, kAdjThreads, 4>(psi, lp, sp, base, tsize);
-        tile_store<T, kAdjThreads, 4>(lam, ll, sp, base, tsize);
-        __syncthreads();
     }
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x)
         partials[(size_t)(slot0 + i) * gridDim.x + blockIdx.x] = slot_acc[i];
