@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import ctypes
 import json
+import math
 import os
 import sys
 import time
@@ -275,6 +276,46 @@ def timed(fn, steps, torch):
     return time.perf_counter() - t0
 
 
+def qft_sweep(args, torch, sv):
+    """The paper's benchmarking procedure (Sec. 3): for every sample, the QFT
+    for every qubit count 1..N in a seeded random order, each timed from
+    register creation to the end of its work, through the register interface
+    (cu1 and h queued, then one tiled run).  Reports the median time per
+    qubit count and the sweep's gate-amplitude updates/s."""
+    nmax = args.sweep_max
+    rng = np.random.default_rng(args.seed)
+    times = {n: [] for n in range(1, nmax + 1)}
+
+    def one(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reg = sv.State(n, "c64")
+        for j in range(n):
+            for k in range(j):
+                reg.cu1(j, k, math.pi / float(2 ** (j - k)))
+            reg.h(j)
+        reg.sync()
+        dt = time.perf_counter() - t0
+        reg.close()
+        return dt
+
+    for _ in range(max(1, args.warmup)):
+        for n in rng.permutation(np.arange(1, nmax + 1)):
+            one(int(n))
+    for _ in range(args.steps):
+        for n in rng.permutation(np.arange(1, nmax + 1)):
+            times[int(n)].append(one(int(n)))
+    med = {n: float(np.median(v)) for n, v in times.items()}
+    updates = sum((1 << n) * (n + n * (n - 1) // 4) for n in range(1, nmax + 1))
+    total = sum(med.values())
+    return {"value": updates / total, "dtype": "f32",
+            "config": {"workload": f"QFT on 1..{nmax} qubits in random order per sample (the paper's "
+                                   "benchmarking procedure), complex64, register interface, "
+                                   f"{args.steps} samples"},
+            "ms_per_step": total * 1e3,
+            "median_s_per_qubit_count": {str(n): med[n] for n in sorted(med)}}
+
+
 def other_workload(args):
     """Fusion (30 qubits, depth 40, complex64, fused at k = 4 and 5), batch
     (4096 ladder-ansatz circuits of 10..20 qubits, one graph launch) or
@@ -336,6 +377,8 @@ def other_workload(args):
                               "how": "per circuit: sv_set_basis, sv_run (tile passes), sv_expectation",
                               "max_abs_diff_z0_vs_batch": float(np.max(np.abs(z_plain - z_batch)))},
                     "speedup_vs_plain": dtp / dt2})
+    elif args.workload == "qft_sweep":
+        out.update(qft_sweep(args, torch, sv))
     else:
         from paper_1805_00988_amd.autograd import ExpectationCircuit
         circ, masks, coeffs = C.config4(seed=args.seed)
@@ -366,9 +409,11 @@ def main():
     ap.add_argument("--fused-prec", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="matrix-core arithmetic of complex64 fused blocks")
     ap.add_argument("--workload", default="plain-at-scale",
-                    choices=["plain-at-scale", "fusion", "batch", "adjoint"],
+                    choices=["plain-at-scale", "fusion", "batch", "adjoint", "qft_sweep"],
                     help="plain-at-scale (default headline line); the others time the "
-                         "fusion, batched and adjoint workloads on their own")
+                         "fusion, batched, adjoint and QFT-sweep workloads on their own")
+    ap.add_argument("--sweep-max", type=int, default=24,
+                    help="largest qubit count of the QFT sweep workload")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -303,14 +303,39 @@ class Batch:
 
 # ------------------------------------------------------------------ State
 
+class _Op:
+    """A queued gate in the form ops_from_gates reads."""
+
+    __slots__ = ("name", "targets", "controls", "theta", "param", "matrix")
+
+    def __init__(self, name, targets, controls=(), theta=0.0, matrix=None):
+        self.name = name
+        self.targets = tuple(int(q) for q in targets)
+        self.controls = tuple(int(q) for q in controls)
+        self.theta = float(theta)
+        self.param = -1
+        self.matrix = matrix
+
+
 class State:
-    """An n-qubit register whose amplitudes live in a torch CUDA tensor."""
+    """An n-qubit register whose amplitudes live in a torch CUDA tensor.
+
+    Besides the entry-point wrappers it offers the register interface of the
+    paper's library (Sec. 2.3 gates, App. B/C usage): gate methods ``h``,
+    ``x``, ``y``, ``z``, ``s``, ``t``, ``rx``, ``ry``, ``rz``, ``u1``,
+    ``cx``, ``cz``, ``cu1`` and ``apply_gate`` queue the gate, as the
+    paper's kernels are queued on a device command queue, and every read of
+    the register (probabilities, amplitudes, measurement, ``sync``) first
+    runs the queued gates in one ``sv_run`` (tile-pass schedule), so
+    consecutive gates share trips of the state through HBM.
+    ``measure(samples=k)`` returns the outcome counts as in App. C."""
 
     def __init__(self, n_qubits: int, dtype="c128", device=None):
         torch = _torch()
         code = _dtype_code(dtype)
         self.n = n_qubits
         self.dtype = code
+        self._pending = []
         tdt = torch.complex64 if code == SV_C64 else torch.complex128
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(dev):
@@ -329,11 +354,75 @@ class State:
         except Exception:
             pass
 
+    # ----------------------------------------------------- queued gates
+    def _queue(self, name, targets, controls=(), theta=0.0, matrix=None) -> "State":
+        for q in tuple(targets) + tuple(controls):
+            if not 0 <= int(q) < self.n:
+                raise ValueError(f"qubit {q} outside the {self.n}-qubit register")
+        self._pending.append(_Op(name, targets, controls, theta, matrix))
+        return self
+
+    def flush(self) -> "State":
+        """Run the queued gates (one sv_run, tile-pass schedule)."""
+        if self._pending:
+            ops, self._pending = self._pending, []
+            sv_run(self.handle, ops, None, SV_RUN_TILED)
+        return self
+
+    def h(self, target: int) -> "State":
+        return self._queue("H", (target,))
+
+    def x(self, target: int) -> "State":
+        return self._queue("X", (target,))
+
+    def y(self, target: int) -> "State":
+        return self._queue("Y", (target,))
+
+    def z(self, target: int) -> "State":
+        return self._queue("Z", (target,))
+
+    def s(self, target: int) -> "State":
+        return self._queue("S", (target,))
+
+    def t(self, target: int) -> "State":
+        return self._queue("T", (target,))
+
+    def rx(self, target: int, theta: float) -> "State":
+        return self._queue("RX", (target,), (), theta)
+
+    def ry(self, target: int, theta: float) -> "State":
+        return self._queue("RY", (target,), (), theta)
+
+    def rz(self, target: int, theta: float) -> "State":
+        return self._queue("RZ", (target,), (), theta)
+
+    def u1(self, target: int, theta: float) -> "State":
+        return self._queue("U1", (target,), (), theta)
+
+    def cx(self, control: int, target: int) -> "State":
+        return self._queue("X", (target,), (control,))
+
+    def cz(self, control: int, target: int) -> "State":
+        return self._queue("Z", (target,), (control,))
+
+    def cu1(self, control: int, target: int, theta: float) -> "State":
+        """diag(1, 1, 1, e^{i theta}) on (control, target) (symmetric)."""
+        return self._queue("U1", (target,), (control,), theta)
+
+    def apply_gate(self, U, target, controls: Iterable[int] = ()) -> "State":
+        """A 2x2 (one target) or 4x4 (two targets, bit j of the matrix index
+        = targets[j]) unitary, optionally controlled."""
+        targets = (target,) if np.isscalar(target) else tuple(target)
+        return self._queue("U", targets, tuple(controls), 0.0, np.asarray(U, dtype=np.complex128))
+
+    # ----------------------------------------------------- entry points
     def set_basis(self, x: int) -> "State":
+        self._pending = []
         sv_set_basis(self.handle, x)
         return self
 
     def apply(self, U, targets, controls: Iterable[int] = ()) -> "State":
+        self.flush()
         mask = 0
         for c in controls:
             mask |= 1 << c
@@ -341,35 +430,63 @@ class State:
         return self
 
     def apply_fused(self, U, qubits, prec: int = SV_PREC_NATIVE) -> "State":
+        self.flush()
         sv_apply_fused(self.handle, list(qubits), U, prec)
         return self
 
     def run(self, gates, params=None, mode: int = SV_RUN_TILED) -> "State":
+        self.flush()
         sv_run(self.handle, gates, params, mode)
         return self
 
     def run_fused(self, gates, k_max: int = 5, prec: int = SV_PREC_FP32, params=None) -> int:
+        self.flush()
         return sv_run_fused(self.handle, gates, k_max, prec, params)
 
     def probabilities(self, out=None) -> float:
+        self.flush()
         return sv_probabilities(self.handle, out)
 
     def expectation(self, z_masks, coeffs) -> float:
+        self.flush()
         return sv_expectation(self.handle, z_masks, coeffs)
 
     def marginals(self, mask: int) -> np.ndarray:
+        self.flush()
         return sv_marginals(self.handle, mask)
 
     def collapse(self, mask: int, value: int) -> float:
+        self.flush()
         return sv_collapse(self.handle, mask, value)
 
-    def measure(self, mask: int, u: float) -> Tuple[int, float]:
+    def measure(self, mask: Optional[int] = None, u: Optional[float] = None, *, samples: Optional[int] = None,
+                seed: int = 0):
+        """``measure(mask, u)``: measure the qubits of ``mask`` with the
+        uniform ``u`` (outcome, probability; the register collapses).
+        ``measure(samples=k)``: k samples of all qubits drawn from the
+        register without changing it, returned as counts keyed by the
+        outcome's bit string (qubit n-1 first); the uniforms come from
+        numpy's generator seeded with ``seed``."""
+        self.flush()
+        if samples is not None:
+            if mask is not None or u is not None:
+                raise ValueError("measure takes either (mask, u) or samples")
+            uniforms = np.random.default_rng(seed).random(int(samples))
+            counts = {}
+            for x in sv_sample(self.handle, uniforms):
+                key = format(int(x), f"0{self.n}b")
+                counts[key] = counts.get(key, 0) + 1
+            return counts
+        if mask is None or u is None:
+            raise ValueError("measure takes either (mask, u) or samples")
         return sv_measure(self.handle, mask, u)
 
     def sample(self, uniforms) -> np.ndarray:
+        self.flush()
         return sv_sample(self.handle, uniforms)
 
     def sync(self) -> "State":
+        self.flush()
         sv_sync(self.handle)
         return self
 
