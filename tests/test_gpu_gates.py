@@ -77,6 +77,33 @@ def test_controlled_gates(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [9, 16])
+def test_multi_controlled_gates_tiled(dtype, n):
+    """Tile passes of gates with 0-3 controls of every kind (general, real,
+    real-diagonal/imaginary-off-diagonal, exchange, diagonal, 4x4), so that
+    controls fall on register positions, on lane bits and on qubits outside
+    the tile, against the oracle."""
+    rng = np.random.default_rng(40 + n)
+    gates = []
+    for i in range(180):
+        nc = int(rng.integers(0, 4))
+        two = i % 9 == 8
+        qs = [int(q) for q in rng.choice(n, size=(2 if two else 1) + nc, replace=False)]
+        ctrl = tuple(qs[2 if two else 1:])
+        if two:
+            gates.append(C.Gate("U", (qs[0], qs[1]), ctrl, 0.0, -1, C.random_unitary(4, rng)))
+            continue
+        name = ["U", "H", "RX", "X", "Y", "T", "RZ", "RY"][int(rng.integers(0, 8))]
+        th = float(rng.uniform(0, 6.28))
+        if name == "U":
+            gates.append(C.Gate("U", (qs[0],), ctrl, 0.0, -1, C.random_unitary(2, rng)))
+        else:
+            gates.append(C.Gate(name, (qs[0],), ctrl, th if name in ("RX", "RZ", "RY") else None))
+    got, ref = run_both(n, dtype, gates, seed=41, mode=sv.SV_RUN_TILED)
+    assert_state_close(got, ref, dtype, len(gates))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_two_qubit_gates_all_pairs(dtype):
     n = 6
     rng = np.random.default_rng(8)
