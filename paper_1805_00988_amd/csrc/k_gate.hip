@@ -458,8 +458,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v,
     extern __shared__ char lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(lds_raw);
     cpx<T> *state = reinterpret_cast<cpx<T> *>(v);
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint64_t base = tile << sp.L;
+    // 32-bit tile counter (at most 2^27 tiles): the loop test stays on the
+    // scalar unit
+    const uint32_t nt = (uint32_t)n_tiles;
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        uint64_t base = (uint64_t)tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
         tile_pass_direct<T, W, TWOQ>(state, lds, sp, base, m, sweeps, n_sweeps, recs, direct);
     }
