@@ -46,6 +46,17 @@ __device__ __forceinline__ uint64_t tile_base(const TileSpec &sp, uint64_t tile)
     return base;
 }
 
+// Byte offset of the operand variant a block uses in the tile at 'base':
+// bit i of the variant index is the tile's value of the i-th lowest qubit of
+// the block's vmask (qubits outside the tile, fixed within it).  Uniform per
+// tile, so it stays on the scalar unit.
+__device__ __forceinline__ int64_t variant_offset(const DenseBlock &B, uint64_t base) {
+    uint32_t v = 0;
+    int i = 0;
+    for (uint64_t vm = B.vmask; vm; vm &= vm - 1, ++i) v |= (uint32_t)((base >> __builtin_ctzll(vm)) & 1ull) << i;
+    return (int64_t)v * B.vstride;
+}
+
 // ------------------------------------------------- native (vector ALU)
 // One thread per group: the 2^K amplitudes go to registers, every output is
 // a dot product with a row of U (uniform across the wave, read through the
@@ -67,7 +78,7 @@ __global__ __launch_bounds__(256) void k_dense_native(typename Amp16<T>::type *v
         __syncthreads();
         for (int b = 0; b < n_blocks; ++b) {
             const DenseBlock &B = blocks[b];
-            const cpx<T> *U = reinterpret_cast<const cpx<T> *>(base_ptr + B.op_off);
+            const cpx<T> *U = reinterpret_cast<const cpx<T> *>(base_ptr + B.op_off + variant_offset(B, base));
             uint32_t PF[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) PF[j] = lds_phys<T>(deposit((uint32_t)j, B.bp.qpos, K));
@@ -392,7 +403,7 @@ __global__ __launch_bounds__((EngCfg<ENG, K>::threads)) void k_dense_mfma(
             const uint32_t *tab = reinterpret_cast<const uint32_t *>(base_ptr + B.tab_off);
             const uint64_t *gtab = reinterpret_cast<const uint64_t *>(base_ptr + B.gtab_off);
             const BlockTabs t{tab, tab + (1 << K), gtab, gtab + (1 << K)};
-            const char *op = base_ptr + B.op_off;
+            const char *op = base_ptr + B.op_off + variant_offset(B, base);
             const bool sg = b == 0 && dfirst, dg = b == n_blocks - 1 && dlast;
             if (sg && dg) apply_block_t<ENG, K, true, true>(lds, state, base, op, t, n_wt, wave, nwaves);
             else if (sg) apply_block_t<ENG, K, true, false>(lds, state, base, op, t, n_wt, wave, nwaves);

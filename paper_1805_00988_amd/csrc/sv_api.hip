@@ -790,16 +790,24 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
 // ================================================================ fusion
 // A dense block: qubits ascending (bit j of the matrix index <-> q[j]) and its
 // 2^k x 2^k matrix, row-major, FP64.
+// In a fused tile pass a block may also depend on qubits outside the tile
+// (vmask, at most kMaxVariantQubits): the diagonal gates fused into it reduce,
+// for each value v of those qubits, to diagonals on the block's own qubits,
+// and var[v] is the block's matrix for that value (bit i of v = the i-th
+// lowest qubit of vmask).
 struct Block {
     int k = 0;
     int q[5] = {0, 0, 0, 0, 0};
     std::vector<std::complex<double>> M;
     int n_gates = 0;
+    uint64_t vmask = 0;
+    std::vector<std::vector<std::complex<double>>> var;
 };
 
-// Left-multiply the block matrix by gate g embedded in the block's qubits:
-// each column of M is a 2^k-amplitude vector and g acts on it as on a state.
-static void absorb(Block &b, const Gate &g) {
+// Left-multiply M (a matrix on the block's qubits) by gate g embedded in
+// them: each column of M is a 2^k-amplitude vector and g acts on it as on a
+// state.
+static void absorb_into(const Block &b, std::vector<std::complex<double>> &M, const Gate &g) {
     const int D = 1 << b.k;
     auto local = [&](int q) {
         for (int j = 0; j < b.k; ++j)
@@ -817,9 +825,9 @@ static void absorb(Block &b, const Gate &g) {
             if (((uint32_t)a & lctrl) != lctrl) continue;
             const int c = a | (1 << t);
             for (int col = 0; col < D; ++col) {
-                const std::complex<double> x0 = b.M[(size_t)a * D + col], x1 = b.M[(size_t)c * D + col];
-                b.M[(size_t)a * D + col] = G[0] * x0 + G[1] * x1;
-                b.M[(size_t)c * D + col] = G[2] * x0 + G[3] * x1;
+                const std::complex<double> x0 = M[(size_t)a * D + col], x1 = M[(size_t)c * D + col];
+                M[(size_t)a * D + col] = G[0] * x0 + G[1] * x1;
+                M[(size_t)c * D + col] = G[2] * x0 + G[3] * x1;
             }
         }
     } else {
@@ -830,16 +838,52 @@ static void absorb(Block &b, const Gate &g) {
             const int idx[4] = {a, a | (1 << t0), a | (1 << t1), a | (1 << t0) | (1 << t1)};
             for (int col = 0; col < D; ++col) {
                 std::complex<double> x[4], y[4];
-                for (int r = 0; r < 4; ++r) x[r] = b.M[(size_t)idx[r] * D + col];
+                for (int r = 0; r < 4; ++r) x[r] = M[(size_t)idx[r] * D + col];
                 for (int r = 0; r < 4; ++r) {
                     y[r] = 0;
                     for (int c = 0; c < 4; ++c) y[r] += G[4 * r + c] * x[c];
                 }
-                for (int r = 0; r < 4; ++r) b.M[(size_t)idx[r] * D + col] = y[r];
+                for (int r = 0; r < 4; ++r) M[(size_t)idx[r] * D + col] = y[r];
             }
         }
     }
+}
+
+static void absorb(Block &b, const Gate &g) {
+    absorb_into(b, b.M, g);
     b.n_gates += 1;
+}
+
+// Whether g's matrix is diagonal (then g multiplies each basis state by a
+// phase and commutes with every other diagonal gate).
+static bool is_diag_gate(const Gate &g) {
+    const int D = 1 << g.k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c)
+            if (r != c && !is_zero(g.U + 2 * (r * D + c))) return false;
+    return true;
+}
+
+// Left-multiply M by the diagonal gate g with the block's outside qubits
+// (vmask) fixed to variant v: basis state a of the block's qubits is scaled
+// by g's diagonal entry at the targets' values when all controls are 1.
+static void absorb_phase(const Block &b, std::vector<std::complex<double>> &M, const Gate &g, uint32_t v) {
+    const int D = 1 << b.k;
+    auto value = [&](int q, int a) -> uint32_t {
+        for (int j = 0; j < b.k; ++j)
+            if (b.q[j] == q) return ((uint32_t)a >> j) & 1u;
+        const int rank = __builtin_popcountll(b.vmask & ((1ull << q) - 1ull));
+        return (v >> rank) & 1u;
+    };
+    const int Dg = 1 << g.k;
+    for (int a = 0; a < D; ++a) {
+        bool on = true;
+        for (uint64_t c = g.ctrl; c; c &= c - 1) on = on && value(__builtin_ctzll(c), a);
+        if (!on) continue;
+        const uint32_t r = value(g.t[0], a) | (g.k == 2 ? value(g.t[1], a) << 1 : 0u);
+        const std::complex<double> d{g.U[2 * (r * Dg + r)], g.U[2 * (r * Dg + r) + 1]};
+        for (int col = 0; col < D; ++col) M[(size_t)a * D + col] *= d;
+    }
 }
 
 // Commutation-aware greedy fusion: scan the unplaced gates in order; a gate
@@ -875,6 +919,56 @@ static std::vector<Block> fuse(const std::vector<Gate> &gs, int k_max) {
         b.M.assign((size_t)D * D, 0.0);
         for (int i = 0; i < D; ++i) b.M[(size_t)i * D + i] = 1.0;
         for (int gi : members) absorb(b, gs[gi]);
+        out.push_back(std::move(b));
+        while (first < gs.size() && done[first]) ++first;
+    }
+    return out;
+}
+
+// Fusion of one tile pass's gates, the tile holding qubits S.  Every qubit
+// of a non-diagonal gate is in the tile; a diagonal gate may also act on
+// qubits outside it, which no other gate of the pass touches except other
+// diagonal gates (all of which commute), so only a gate's qubits inside the
+// tile order it against the others and count towards k_max.  Its qubits
+// outside the tile join the block's variant qubits (at most
+// kMaxVariantQubits; the scheduler lets only diagonal gates of at most that
+// many qubits leave the tile).
+static std::vector<Block> fuse_tile(const std::vector<Gate> &gs, int k_max, uint64_t S) {
+    std::vector<Block> out;
+    std::vector<char> done(gs.size(), 0);
+    size_t first = 0;
+    while (first < gs.size()) {
+        uint64_t set = 0, vset = 0, blocked = 0;
+        std::vector<int> members;
+        for (size_t i = first; i < gs.size(); ++i) {
+            if (done[i]) continue;
+            const uint64_t gin = gs[i].qmask() & S, gout = gs[i].qmask() & ~S;
+            if (gin & blocked) {
+                blocked |= gin;
+                continue;
+            }
+            if (__builtin_popcountll(set | gin) <= k_max && __builtin_popcountll(vset | gout) <= kMaxVariantQubits) {
+                set |= gin;
+                vset |= gout;
+                members.push_back((int)i);
+                done[i] = 1;
+            } else {
+                blocked |= gin;
+            }
+        }
+        Block b;
+        for (uint64_t m = set; m; m &= m - 1) b.q[b.k++] = __builtin_ctzll(m);
+        b.vmask = vset;
+        const int D = 1 << b.k;
+        std::vector<std::complex<double>> I((size_t)D * D, 0.0);
+        for (int i = 0; i < D; ++i) I[(size_t)i * D + i] = 1.0;
+        b.var.assign((size_t)1 << __builtin_popcountll(vset), I);
+        for (uint32_t v = 0; v < b.var.size(); ++v)
+            for (int gi : members) {
+                if (gs[gi].qmask() & ~S) absorb_phase(b, b.var[v], gs[gi], v);
+                else absorb_into(b, b.var[v], gs[gi]);
+            }
+        b.n_gates = (int)members.size();
         out.push_back(std::move(b));
         while (first < gs.size() && done[first]) ++first;
     }
@@ -995,7 +1089,8 @@ struct FusedPass {
     int engine = SV_PREC_NATIVE;
     uint32_t direct = 0; // kDirectFirst / kDirectLast (matrix cores)
     std::vector<DenseBlock> blocks;
-    std::vector<std::vector<std::complex<double>>> mats;
+    // per block, its padded matrix for each variant of its outside qubits
+    std::vector<std::vector<std::vector<std::complex<double>>>> mats;
 };
 
 // engine: the launch_dense_pass precision code of a pass (SV_PREC_NATIVE =
@@ -1019,8 +1114,8 @@ static size_t dense_tab_entries(int k, int m, int engine) {
     const size_t rows = (size_t)mfma_rows(k, engine);
     return ((size_t)1 << k) + rows + (((size_t)1 << (m - k)) / rows);
 }
-static size_t dense_op_bytes(const sv_state *h, int k, int m, int engine) {
-    size_t b = dense_frag_bytes(h, k, engine);
+static size_t dense_op_bytes(const sv_state *h, int k, int m, int engine, size_t n_variants) {
+    size_t b = n_variants * dense_frag_bytes(h, k, engine);
     if (is_mfma(engine)) {
         b += align256(dense_tab_entries(k, m, engine) * sizeof(uint32_t));
         b += align256(dense_tab_entries(k, m, engine) * sizeof(uint64_t));
@@ -1037,8 +1132,9 @@ static uint64_t tile_global_offset(const TileSpec &sp, uint32_t l) {
 }
 
 static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp) {
-    return align256(fp.blocks.size() * sizeof(DenseBlock)) +
-           fp.blocks.size() * dense_op_bytes(h, fp.k, fp.m, fp.engine);
+    size_t b = align256(fp.blocks.size() * sizeof(DenseBlock));
+    for (const auto &vs : fp.mats) b += dense_op_bytes(h, fp.k, fp.m, fp.engine, vs.size());
+    return b;
 }
 
 // Embed a k-qubit matrix in K qubits (extra index bits k..K-1 act as identity).
@@ -1058,21 +1154,16 @@ static std::vector<std::complex<double>> pad_matrix(const std::vector<std::compl
 // cost per pass (measured on complex64)
 static int fused_lmin(const sv_state *h) { return std::min(h->n, 5); }
 
-// One fused pass over the blocks bs[idx] (all their qubits fit in one tile).
-// Blocks run on the matrix cores in the requested precision (the state's own
-// for SV_PREC_NATIVE) whenever the tile holds whole wave-tiles; narrower
-// blocks are then padded to 4 qubits.
-static FusedPass build_fused_pass(const sv_state *h, const std::vector<Block> &bs, const std::vector<int> &idx,
-                                  int prec) {
-    const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
+// One fused pass over the blocks bs[idx] in the tile layout sp (which holds
+// all their qubits).  Blocks run on the matrix cores in the requested
+// precision (the state's own for SV_PREC_NATIVE) whenever the tile holds
+// whole wave-tiles; narrower blocks are then padded to 4 qubits.
+static FusedPass build_fused_pass(const sv_state *h, const TileSpec &sp, const std::vector<Block> &bs,
+                                  const std::vector<int> &idx, int prec) {
     FusedPass fp;
-    uint64_t needed = 0;
-    int kmax = 0;
-    for (int bi : idx) {
-        for (int j = 0; j < bs[bi].k; ++j) needed |= 1ull << bs[bi].q[j];
-        kmax = std::max(kmax, bs[bi].k);
-    }
-    tile_layout(h->n, mmax, fused_lmin(h), needed, &fp.sp);
+    int kmax = 1;
+    for (int bi : idx) kmax = std::max(kmax, bs[bi].k);
+    fp.sp = sp;
     fp.m = fp.sp.L + fp.sp.K;
     const int K = std::max(4, kmax);
     if (h->dtype == SV_C64) {
@@ -1103,8 +1194,12 @@ static FusedPass build_fused_pass(const sv_state *h, const std::vector<Block> &b
         db.bp.ng = 0;
         for (int b = 0; b < fp.m; ++b)
             if (!((used >> b) & 1u)) db.bp.gpos[db.bp.ng++] = b;
+        db.vmask = B.vmask;
         fp.blocks.push_back(db);
-        fp.mats.push_back(B.k == fp.k ? B.M : pad_matrix(B.M, B.k, fp.k));
+        std::vector<std::vector<std::complex<double>>> vs;
+        for (const auto &M : B.var.empty() ? std::vector<std::vector<std::complex<double>>>{B.M} : B.var)
+            vs.push_back(B.k == fp.k ? M : pad_matrix(M, B.k, fp.k));
+        fp.mats.push_back(std::move(vs));
         fp.flops_per_amp += 8.0 * (double)(1 << B.k);
     }
     return fp;
@@ -1120,68 +1215,100 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
         for (int j = 0; j < bs[b].k; ++j) tm[b] |= 1ull << bs[b].q[j];
     }
     std::vector<FusedPass> out;
-    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h))) out.push_back(build_fused_pass(h, bs, p.gates, prec));
+    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h))) {
+        uint64_t needed = 0;
+        for (int bi : p.gates) needed |= tm[bi];
+        TileSpec sp{};
+        tile_layout(h->n, mmax, fused_lmin(h), needed, &sp);
+        out.push_back(build_fused_pass(h, sp, bs, p.gates, prec));
+    }
     return out;
 }
 
+// Qubits a tile layout holds.
+static uint64_t tile_qubits(const TileSpec &sp) {
+    uint64_t S = sp.L >= 64 ? ~0ull : ((1ull << sp.L) - 1ull);
+    for (int i = 0; i < sp.K; ++i) S |= 1ull << sp.high[i];
+    return S;
+}
+
 // Tile-aware fusion of a gate list: the tile scheduler first groups the
-// gates into passes (every qubit of a gate, controls included, in the
-// tile), then each pass's gates are fused into blocks of at most k_max
-// qubits, so all blocks of a pass share one trip of the state through LDS.
+// gates into passes, then each pass's gates are fused into blocks of at most
+// k_max qubits, so all blocks of a pass share one trip of the state through
+// LDS.  Every qubit of a non-diagonal gate, controls included, must be in
+// the tile; a diagonal gate of at most kMaxVariantQubits qubits needs none
+// of its qubits there (those outside select a variant of its block's
+// matrix per tile).
 static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::vector<Gate> &gs, int k_max,
                                                   int prec, int *n_blocks) {
     const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
-    std::vector<uint64_t> qm(gs.size());
-    for (size_t i = 0; i < gs.size(); ++i) qm[i] = gs[i].qmask();
+    std::vector<uint64_t> tm(gs.size()), qm(gs.size());
+    for (size_t i = 0; i < gs.size(); ++i) {
+        qm[i] = gs[i].qmask();
+        const bool outside_ok = is_diag_gate(gs[i]) && __builtin_popcountll(qm[i]) <= kMaxVariantQubits;
+        tm[i] = outside_ok ? 0 : qm[i];
+    }
     std::vector<FusedPass> out;
     *n_blocks = 0;
-    for (const Pass &p : schedule_masks(qm, qm, mmax, fused_lmin(h))) {
+    for (const Pass &p : schedule_masks(tm, qm, mmax, fused_lmin(h))) {
+        uint64_t needed = 0;
         std::vector<Gate> sub;
         sub.reserve(p.gates.size());
-        for (int gi : p.gates) sub.push_back(gs[gi]);
-        const std::vector<Block> bs = fuse(sub, k_max);
+        for (int gi : p.gates) {
+            needed |= tm[gi];
+            sub.push_back(gs[gi]);
+        }
+        TileSpec sp{};
+        tile_layout(h->n, mmax, fused_lmin(h), needed, &sp);
+        const std::vector<Block> bs = fuse_tile(sub, k_max, tile_qubits(sp));
         std::vector<int> idx(bs.size());
         for (size_t b = 0; b < bs.size(); ++b) idx[b] = (int)b;
-        out.push_back(build_fused_pass(h, bs, idx, prec));
+        out.push_back(build_fused_pass(h, sp, bs, idx, prec));
         *n_blocks += (int)bs.size();
     }
     return out;
 }
 
-// Write a fused pass (block records, then one operand per block) at 'off';
-// operand offsets are relative to the arena base.
+// Write a fused pass (block records, then per block its operand variants
+// and offset tables) at 'off'; operand offsets are relative to the arena
+// base.
 static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
     const size_t fb = dense_frag_bytes(h, fp.k, fp.engine);
-    const size_t ob = dense_op_bytes(h, fp.k, fp.m, fp.engine);
     const int ab = h->dtype == SV_C64 ? 8 : 16;
     size_t opo = off + align256(fp.blocks.size() * sizeof(DenseBlock));
-    for (size_t b = 0; b < fp.blocks.size(); ++b, opo += ob) {
+    for (size_t b = 0; b < fp.blocks.size(); ++b) {
         DenseBlock &db = fp.blocks[b];
+        const size_t nvar = fp.mats[b].size();
         db.op_off = (int64_t)opo;
+        db.vstride = (int64_t)fb;
         db.tab_off = 0;
         db.gtab_off = 0;
-        char *dst = h->h_arena + opo;
-        const std::complex<double> *U = fp.mats[b].data();
-        if (fp.engine == kPrecMfma64) {
-            make_fragments64(U, fp.k, dst);
-        } else if (fp.engine != SV_PREC_NATIVE) {
-            make_fragments(U, fp.k, fp.engine, dst);
-        } else if (h->dtype == SV_C64) {
-            float *f = reinterpret_cast<float *>(dst);
-            for (size_t i = 0; i < fp.mats[b].size(); ++i) {
-                f[2 * i] = (float)U[i].real();
-                f[2 * i + 1] = (float)U[i].imag();
-            }
-        } else {
-            double *d = reinterpret_cast<double *>(dst);
-            for (size_t i = 0; i < fp.mats[b].size(); ++i) {
-                d[2 * i] = U[i].real();
-                d[2 * i + 1] = U[i].imag();
+        for (size_t v = 0; v < nvar; ++v) {
+            char *dst = h->h_arena + opo + v * fb;
+            const std::vector<std::complex<double>> &Mv = fp.mats[b][v];
+            const std::complex<double> *U = Mv.data();
+            if (fp.engine == kPrecMfma64) {
+                make_fragments64(U, fp.k, dst);
+            } else if (fp.engine != SV_PREC_NATIVE) {
+                make_fragments(U, fp.k, fp.engine, dst);
+            } else if (h->dtype == SV_C64) {
+                float *f = reinterpret_cast<float *>(dst);
+                for (size_t i = 0; i < Mv.size(); ++i) {
+                    f[2 * i] = (float)U[i].real();
+                    f[2 * i + 1] = (float)U[i].imag();
+                }
+            } else {
+                double *d = reinterpret_cast<double *>(dst);
+                for (size_t i = 0; i < Mv.size(); ++i) {
+                    d[2 * i] = U[i].real();
+                    d[2 * i + 1] = U[i].imag();
+                }
             }
         }
+        const size_t tabs = opo + nvar * fb;
         if (is_mfma(fp.engine)) {
-            db.tab_off = (int64_t)(opo + fb);
-            uint32_t *qoff = reinterpret_cast<uint32_t *>(h->h_arena + opo + fb);
+            db.tab_off = (int64_t)tabs;
+            uint32_t *qoff = reinterpret_cast<uint32_t *>(h->h_arena + tabs);
             uint32_t *goff = qoff + (1u << fp.k);
             auto deposit = [](uint32_t x, const int *pos, int nb) {
                 uint32_t r = 0;
@@ -1196,7 +1323,7 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
             for (uint32_t w = 0; w < (1u << (fp.m - fp.k)) / rows; ++w)
                 ghi[w] = lds_swizzle(deposit(w * rows, db.bp.gpos, db.bp.ng), ab);
             // the same tables as global offsets
-            db.gtab_off = (int64_t)(opo + fb + align256(dense_tab_entries(fp.k, fp.m, fp.engine) * sizeof(uint32_t)));
+            db.gtab_off = (int64_t)(tabs + align256(dense_tab_entries(fp.k, fp.m, fp.engine) * sizeof(uint32_t)));
             uint64_t *gq = reinterpret_cast<uint64_t *>(h->h_arena + db.gtab_off);
             uint64_t *gg = gq + (1u << fp.k);
             for (uint32_t j = 0; j < (1u << fp.k); ++j) gq[j] = tile_global_offset(fp.sp, deposit(j, db.bp.qpos, fp.k));
@@ -1204,6 +1331,7 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
             for (uint32_t w = 0; w < (1u << (fp.m - fp.k)) / rows; ++w)
                 gg[rows + w] = tile_global_offset(fp.sp, deposit(w * rows, db.bp.gpos, db.bp.ng));
         }
+        opo += dense_op_bytes(h, fp.k, fp.m, fp.engine, nvar);
     }
     std::memcpy(h->h_arena + off, fp.blocks.data(), fp.blocks.size() * sizeof(DenseBlock));
 }

@@ -187,12 +187,21 @@ struct BlockPos {
 // goff_hi[w] ^ goff_lo[i] ^ qoff[j].  gtab_off: the same three tables as
 // uint64 global index offsets from the tile's base (OR-combined), for the
 // blocks that read or write the state directly.
+// vmask: qubits outside the tile on which the block's matrix depends (the
+// diagonal gates fused into it may act on qubits the tile does not hold;
+// within one tile those qubits are fixed, so the gate reduces to a diagonal
+// on the block's own qubits).  The operand of variant v, bit i of v = value
+// of the i-th lowest qubit of vmask in the tile's base index, starts at
+// op_off + v * vstride.
+constexpr int kMaxVariantQubits = 4;
 struct DenseBlock {
     BlockPos bp;
     int32_t pad;
     int64_t op_off;
     int64_t tab_off;
     int64_t gtab_off;
+    uint64_t vmask;
+    int64_t vstride;
 };
 // launch_dense_pass precision code for complex128 blocks on the FP64 matrix cores
 constexpr int kPrecMfma64 = 100;

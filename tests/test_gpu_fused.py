@@ -94,6 +94,54 @@ def test_run_fused_qft_and_cnot_circuits(dtype, prec):
         check(st.numpy(), O.run(circ), dtype, prec, 5, nb)
 
 
+def diagonal_rich_circuit(n, seed, layers=6):
+    """Dense one-qubit layers interleaved with diagonal gates of 1-5 qubits
+    (controlled phases, controlled RZ, two-qubit diagonal matrices with
+    controls), whose qubits are spread over the whole register so that many
+    of them lie outside a fused pass's tile."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            gates.append(C.Gate(str(rng.choice(["H", "RX", "RY"])), (q,), theta=float(rng.uniform(0, 2 * math.pi))))
+        for _ in range(n):
+            w = int(rng.integers(1, 6))
+            qs = [int(x) for x in rng.choice(n, size=w, replace=False)]
+            kind = int(rng.integers(0, 3))
+            th = float(rng.uniform(0, 2 * math.pi))
+            if kind == 2 and w >= 2:
+                ph = np.exp(1j * rng.uniform(0, 2 * math.pi, size=4))
+                gates.append(C.Gate("U", (qs[0], qs[1]), tuple(qs[2:]), matrix=np.diag(ph)))
+            else:
+                gates.append(C.Gate("U1" if kind == 0 else "RZ", (qs[0],), tuple(qs[1:]), theta=th))
+    return C.Circuit(n, gates, 0, None, f"diag_rich_n{n}_s{seed}")
+
+
+@pytest.mark.parametrize("dtype,prec", [("c128", "native"), ("c64", "native"), ("c64", "fp32"),
+                                        ("c64", "bf16x3")])
+@pytest.mark.parametrize("n", [15, 17])
+def test_run_fused_diagonal_gates_outside_tile(dtype, prec, n):
+    """Diagonal gates may keep qubits outside a fused pass's tile (their
+    blocks then carry one matrix per value of those qubits); the result must
+    still match the oracle."""
+    circ = diagonal_rich_circuit(n, 40 + n)
+    st, psi0 = start(n, dtype, 60 + n)
+    nb = st.run_fused(circ.gates, k_max=5, prec=PRECS[prec])
+    check(st.numpy(), O.run_gates(n, circ.gates, psi0), dtype, prec, 5, nb)
+
+
+@pytest.mark.parametrize("dtype,prec", [("c128", "native"), ("c64", "bf16x3")])
+def test_run_fused_only_outside_diagonals(dtype, prec):
+    """A pass whose gates act only on qubits outside the tile: its blocks have
+    no qubit of their own (a phase per tile), padded to the pass's width."""
+    n = 18
+    gates = [C.Gate("Z", (17,), (16,)), C.Gate("U1", (15,), (17,), theta=0.7),
+             C.Gate("RZ", (16,), theta=1.3), C.Gate("T", (14,)), C.Gate("S", (17,), (14, 15, 16))]
+    st, psi0 = start(n, dtype, 7)
+    nb = st.run_fused(gates, k_max=4, prec=PRECS[prec])
+    check(st.numpy(), O.run_gates(n, gates, psi0), dtype, prec, 4, nb)
+
+
 def test_mfma_rejected_for_complex128():
     st = sv.State(12, "c128")
     with pytest.raises(sv.SVError):
