@@ -4,6 +4,7 @@
 #include "sv_internal.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <complex>
@@ -291,6 +292,13 @@ static int local_bit(const TileSpec &sp, int q) {
     return -1;
 }
 
+// Qubits a tile layout holds.
+static uint64_t tile_qubits(const TileSpec &sp) {
+    uint64_t S = sp.L >= 64 ? ~0ull : ((1ull << sp.L) - 1ull);
+    for (int i = 0; i < sp.K; ++i) S |= 1ull << sp.high[i];
+    return S;
+}
+
 // A tile pass compiled for the device: tile layout, register sweeps and the
 // sweeps' gate records (stored consecutively in sweep order).
 struct PassCode {
@@ -522,15 +530,20 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         // Phase gates whose condition holds at most one register bit are
         // gathered into per-lane factors (all diagonal gates commute) when at
         // least kMinPhaseRun of them follow each other; a flush applies them.
+        // Diagonal gates whose target lies outside the tile (their factor is
+        // uniform over the tile's lanes for each value of the target) are
+        // always gathered.
         std::vector<int> slot(cur.size(), -1);
+        auto outside = [&](const Gate &g) { return is_diag1(g) && local_bit(sp, g.t[0]) < 0; };
         if (!probes) {
             for (size_t a = 0; a < cur.size();) {
                 size_t b = a;
                 while (b < cur.size()) {
                     const Gate &g = *gs[cur[b]];
-                    if (!is_diag1(g) || !is_one(g.U)) break;
+                    if (!is_diag1(g) || !(is_one(g.U) || outside(g))) break;
                     TileGate tmp{};
-                    const uint32_t cond = encode_controls(sp, g.ctrl, &tmp) | (1u << local_bit(sp, g.t[0]));
+                    const int lt = local_bit(sp, g.t[0]);
+                    const uint32_t cond = encode_controls(sp, g.ctrl, &tmp) | (lt >= 0 ? 1u << lt : 0u);
                     const uint32_t reg = cond & fall;
                     if (__builtin_popcount(reg) > 1) break;
                     int s = W;
@@ -540,7 +553,8 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
                     ++b;
                 }
                 if (b - a < (size_t)kMinPhaseRun)
-                    for (size_t c = a; c < b; ++c) slot[c] = -1;
+                    for (size_t c = a; c < b; ++c)
+                        if (!outside(*gs[cur[c]])) slot[c] = -1;
                 a = b == a ? a + 1 : b;
             }
         }
@@ -549,7 +563,8 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         // of the tile is the product of the phases whose condition holds),
         // then a flush.
         uint32_t pending = 0;
-        std::vector<std::pair<std::pair<int, uint32_t>, std::vector<std::pair<uint64_t, const double *>>>> groups;
+        std::vector<std::pair<std::pair<int, uint32_t>, std::vector<std::pair<uint64_t, std::array<double, 2>>>>>
+            groups;
         const size_t entry_bytes = 8 + (f32 ? 8 : 16);
         const int max_entries = (int)(sizeof(TileGate::m) / entry_bytes);
         auto flush = [&]() {
@@ -567,7 +582,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
                     char *dst = reinterpret_cast<char *>(r.m);
                     for (size_t e = 0; e < ne; ++e, dst += entry_bytes) {
                         std::memcpy(dst, &ents[e0 + e].first, 8);
-                        const double *ph = ents[e0 + e].second;
+                        const double *ph = ents[e0 + e].second.data();
                         if (f32) {
                             const float f[2] = {(float)ph[0], (float)ph[1]};
                             std::memcpy(dst + 8, f, 8);
@@ -592,14 +607,24 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
             if (slot[ci] >= 0) {
                 const Gate &g = *gs[i];
                 TileGate r{};
-                const uint32_t cond = encode_controls(sp, g.ctrl, &r) | (1u << local_bit(sp, g.t[0]));
+                const int lt = local_bit(sp, g.t[0]);
+                const uint32_t cond = encode_controls(sp, g.ctrl, &r) | (lt >= 0 ? 1u << lt : 0u);
                 const std::pair<int, uint32_t> key{slot[ci], cond & ~fall};
                 auto it = std::find_if(groups.begin(), groups.end(), [&](const auto &x) { return x.first == key; });
                 if (it == groups.end()) {
                     groups.push_back({key, {}});
                     it = groups.end() - 1;
                 }
-                it->second.push_back({r.cout, g.U + 6});
+                if (lt >= 0) {
+                    it->second.push_back({r.cout, {g.U[6], g.U[7]}});
+                } else {
+                    // target outside the tile: diag(d0, d1) = d0 on the
+                    // condition, times d1 / d0 where the target is 1
+                    const std::complex<double> d0{g.U[0], g.U[1]}, d1{g.U[6], g.U[7]};
+                    if (!is_one(g.U)) it->second.push_back({r.cout, {d0.real(), d0.imag()}});
+                    const std::complex<double> q = is_one(g.U) ? d1 : d1 / d0;
+                    it->second.push_back({r.cout | (1ull << g.t[0]), {q.real(), q.imag()}});
+                }
                 pending |= 1u << slot[ci];
                 pc.flops_per_amp += gate_flops_per_amp(g);
                 continue;
@@ -718,14 +743,43 @@ static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const s
     return passes;
 }
 
-static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, int lmin) {
+// Tile qubits a gate of a plain tile pass needs: its targets, except for
+// phase gates diag(1, e^{i phi}) with any controls (symmetric in their
+// qubits: the target can be any of them, and with none in the tile the
+// factor is uniform per tile) and uncontrolled one-qubit diagonal gates
+// (uniform per tile for each value of the target), which need none.
+static uint64_t tile_need(const Gate &g) {
+    if (is_diag1(g) && (is_one(g.U) || g.ctrl == 0)) return 0;
+    return g.tmask();
+}
+
+// outside_diag: let the gates tile_need exempts leave their targets out of
+// the tile (sv_run's passes; the batch and adjoint passes keep every target
+// in the tile).
+static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, int lmin,
+                                  bool outside_diag = false) {
     (void)n;
     std::vector<uint64_t> tm(gs.size()), qm(gs.size());
     for (size_t i = 0; i < gs.size(); ++i) {
-        tm[i] = gs[i].tmask();
+        tm[i] = outside_diag ? tile_need(gs[i]) : gs[i].tmask();
         qm[i] = gs[i].qmask();
     }
     return schedule_masks(tm, qm, mmax, lmin);
+}
+
+// A phase gate of a pass with its target outside the tile and a control
+// inside: the same gate with that control as the target (the gate is
+// symmetric in its qubits), so that only phase gates with no qubit in the
+// tile keep an outside target.
+static Gate retarget_phase(const Gate &g, uint64_t S) {
+    Gate r = g;
+    const uint64_t in = g.ctrl & S;
+    if (is_diag1(g) && is_one(g.U) && !((S >> g.t[0]) & 1ull) && in) {
+        const int t = __builtin_ctzll(in);
+        r.ctrl = (g.ctrl | (1ull << g.t[0])) & ~(1ull << t);
+        r.t[0] = t;
+    }
+    return r;
 }
 
 // A single gate that the streamed kernels cannot take: a two-qubit gate with
@@ -747,7 +801,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
     // runs of 128 complex64 / 64 complex128 amplitudes: shorter runs cut
     // the number of passes but cost more per pass (measured)
     const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
-    std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin);
+    std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin, true);
     // compile every tiled pass, stage all of them, upload once, launch in order
     std::vector<PassCode> code(passes.size());
     std::vector<size_t> offs(passes.size(), 0);
@@ -758,13 +812,14 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         tiled[pi] = p.gates.size() > 1 || (p.gates.size() == 1 && needs_tile(h, gs[p.gates[0]]));
         if (!tiled[pi]) continue;
         uint64_t needed = 0;
-        std::vector<const Gate *> ptrs;
-        for (int gi : p.gates) {
-            needed |= gs[gi].tmask();
-            ptrs.push_back(&gs[gi]);
-        }
+        for (int gi : p.gates) needed |= tile_need(gs[gi]);
         TileSpec sp{};
         tile_layout(h->n, mmax, lmin, needed, &sp);
+        std::vector<Gate> local;
+        local.reserve(p.gates.size());
+        for (int gi : p.gates) local.push_back(retarget_phase(gs[gi], tile_qubits(sp)));
+        std::vector<const Gate *> ptrs;
+        for (const Gate &g : local) ptrs.push_back(&g);
         code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64);
         offs[pi] = total;
         total += align256(code[pi].bytes());
@@ -1225,12 +1280,6 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
     return out;
 }
 
-// Qubits a tile layout holds.
-static uint64_t tile_qubits(const TileSpec &sp) {
-    uint64_t S = sp.L >= 64 ? ~0ull : ((1ull << sp.L) - 1ull);
-    for (int i = 0; i < sp.K; ++i) S |= 1ull << sp.high[i];
-    return S;
-}
 
 // Tile-aware fusion of a gate list: the tile scheduler first groups the
 // gates into passes, then each pass's gates are fused into blocks of at most

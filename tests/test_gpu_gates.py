@@ -176,6 +176,43 @@ def test_phase_runs_tiled(dtype, n):
     assert_state_close(got, ref, dtype, len(gates))
 
 
+def outside_diagonal_circuit(n, seed, layers=8):
+    """Dense gates on the low qubits only (so that tile passes hold the low
+    qubits) mixed with diagonal gates anywhere: uncontrolled RZ, Z, S, T,
+    phase gates with 0-3 controls, and controlled RZ, in runs of 1 to 8."""
+    rng = np.random.default_rng(seed)
+    lowq = max(1, n // 2)
+    gates = [C.Gate("H", (q,)) for q in range(n)]
+    for _ in range(layers):
+        for q in range(lowq):
+            gates.append(C.Gate(["H", "RX", "RY"][int(rng.integers(0, 3))], (q,), (), float(rng.uniform(0, 6.28))))
+        for _ in range(int(rng.integers(1, 9))):
+            qs = [int(x) for x in rng.choice(n, size=1 + int(rng.integers(0, 4)), replace=False)]
+            kind = int(rng.integers(0, 4))
+            th = float(rng.uniform(0, 6.28))
+            if kind == 0:
+                gates.append(C.Gate(["RZ", "Z", "S", "T"][int(rng.integers(0, 4))], (qs[0],), (), th))
+            elif kind == 1:
+                gates.append(C.Gate("U1", (qs[0],), tuple(qs[1:]), th))
+            elif kind == 2:
+                gates.append(C.Gate(["Z", "S", "T"][int(rng.integers(0, 3))], (qs[0],), tuple(qs[1:])))
+            else:
+                gates.append(C.Gate("RZ", (qs[0],), tuple(qs[1:2]), th))
+    gates += [C.Gate("H", (q,)) for q in range(n)]
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [8, 16, 18])
+def test_diagonal_gates_outside_tile(dtype, n):
+    """Tile passes take phase gates and uncontrolled diagonal gates whatever
+    the tile holds (the target outside the tile gives a factor per tile, a
+    phase gate's target may move to one of its controls)."""
+    gates = outside_diagonal_circuit(n, 90 + n)
+    got, ref = run_both(n, dtype, gates, seed=11, mode=sv.SV_RUN_TILED)
+    assert_state_close(got, ref, dtype, len(gates))
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("mode", ["per_gate", "tiled"])
 def test_config0_random_circuit(dtype, mode):
