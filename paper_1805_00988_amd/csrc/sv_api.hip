@@ -1318,6 +1318,24 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
     return out;
 }
 
+// LDS layout of the complex64 matrix-core passes, which address their tile
+// only through the offset tables (their first block reads the state and
+// their last writes it, so the tile is never staged by the device's own
+// swizzle): the low 5 bits of a tile index (32 amplitudes, one row of the
+// 64 banks) are XOR-ed with a fixed linear function of the higher bits.  The
+// constants were chosen with a bank-conflict model of the blocks' operand
+// and result accesses (64 lanes in two phases of 32, 2 banks per amplitude)
+// over every position of a 4- or 5-qubit block in a 13-qubit tile: 2.5 LDS
+// cycles per access on average and 4 at worst, against 4.3 and 16 for the
+// gate tile's fold (2 is conflict-free).
+static uint32_t mfma_swizzle_c64(uint32_t l) {
+    static const uint32_t H[8] = {29, 19, 30, 7, 11, 27, 31, 22};
+    uint32_t h = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((l >> (5 + i)) & 1u) h ^= H[i];
+    return l ^ h;
+}
+
 // Write a fused pass (block records, then per block its operand variants
 // and offset tables) at 'off'; operand offsets are relative to the arena
 // base.
@@ -1367,10 +1385,12 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
             };
             const uint32_t rows = (uint32_t)mfma_rows(fp.k, fp.engine);
             uint32_t *ghi = goff + rows;
-            for (uint32_t j = 0; j < (1u << fp.k); ++j) qoff[j] = lds_swizzle(deposit(j, db.bp.qpos, fp.k), ab);
-            for (uint32_t g = 0; g < rows; ++g) goff[g] = lds_swizzle(deposit(g, db.bp.gpos, db.bp.ng), ab);
+            const bool own = h->dtype == SV_C64 && fp.direct == (kDirectFirst | kDirectLast) && fp.m <= 13;
+            auto swz = [&](uint32_t l) { return own ? mfma_swizzle_c64(l) : lds_swizzle(l, ab); };
+            for (uint32_t j = 0; j < (1u << fp.k); ++j) qoff[j] = swz(deposit(j, db.bp.qpos, fp.k));
+            for (uint32_t g = 0; g < rows; ++g) goff[g] = swz(deposit(g, db.bp.gpos, db.bp.ng));
             for (uint32_t w = 0; w < (1u << (fp.m - fp.k)) / rows; ++w)
-                ghi[w] = lds_swizzle(deposit(w * rows, db.bp.gpos, db.bp.ng), ab);
+                ghi[w] = swz(deposit(w * rows, db.bp.gpos, db.bp.ng));
             // the same tables as global offsets
             db.gtab_off = (int64_t)(tabs + align256(dense_tab_entries(fp.k, fp.m, fp.engine) * sizeof(uint32_t)));
             uint64_t *gq = reinterpret_cast<uint64_t *>(h->h_arena + db.gtab_off);
