@@ -178,8 +178,14 @@ int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int
  * into passes whose qubits (targets and controls) fit one LDS tile, then the
  * gates of each pass are fused as by sv_fuse into blocks of at most k_max
  * qubits, and every block of a pass is applied, as by sv_apply_fused(prec),
- * during a single read and write of the state.  *n_blocks_out (may be NULL)
- * receives the number of blocks applied. */
+ * during a single read and write of the state.  A diagonal gate of at most
+ * four qubits may keep qubits outside the tile: they are fixed within one
+ * tile, so the block holding the gate carries one matrix per value of its
+ * outside qubits (at most 16) and each tile uses its own.  Only a gate's
+ * qubits inside the tile count towards k_max in a block; every gate must
+ * still touch at most k_max qubits (SV_EINVAL).  *n_blocks_out (may be
+ * NULL) receives the number of blocks applied.  Same result as sv_run up
+ * to rounding (FP32 or split-BF16 products for prec != SV_PREC_NATIVE). */
 int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
                  int k_max, int prec, int *n_blocks_out);
 
