@@ -111,8 +111,10 @@ __device__ void batch_tile(cpx<T> *state, cpx<T> *lds, const TileSpec &sp, int m
             const char *rp = recs + S.rec_off;
             for (int gi = 0; gi < S.n_gates; ++gi) {
                 const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
-                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+                // advance before the gate: its inline assembly would make the
+                // compiler read the size again after it
                 rp += G.size;
+                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
             }
             if (last) {
                 if (last_pass) {

@@ -431,8 +431,10 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
             const char *rp = recs + S.rec_off;
             for (int gi = 0; gi < ng; ++gi) {
                 const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
-                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+                // advance before the gate: its inline assembly would make the
+                // compiler read the size again after it
                 rp += G.size;
+                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
             }
             if (last) {
 #pragma unroll

@@ -578,8 +578,10 @@ __device__ void tile_run_sweeps(cpx<T> *lds, int m, uint64_t base, const TileSwe
             const char *rp = r0;
             for (int gi = 0; gi < ng; ++gi) {
                 const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
-                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+                // advance before the gate: its inline assembly would make the
+                // compiler read the size again after it
                 rp += G.size;
+                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) lds[addr[j]] = v[j];
