@@ -430,7 +430,7 @@ hipError_t launch_dense_pass(void *amps, int n, int dtype, const TileSpec &sp, i
     if (m > n || k > m || k < 1 || k > 5 || n_blocks < 1) return hipErrorInvalidValue;
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
-    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1024);
+    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 30);
     if (prec != SV_PREC_NATIVE) {
         const bool f64 = prec == kPrecMfma64;
         if (f64 != (dtype == SV_C128) || k < 4) return hipErrorInvalidValue;

@@ -351,13 +351,19 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
 // tile and tested once on its base index.
 constexpr int kTileThreads = 512;
 
-// 64 KiB of LDS, two workgroups per CU.  (Tiles of 128 KiB with 1024 threads
-// took fewer passes but more time per gate: slower overall.)
-int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
-int batch_tile_qubits(int dtype) { return tile_max_qubits(dtype); }
+// Tiles of 4096 amplitudes: 32 KiB of LDS for complex64 (five 256-thread
+// workgroups per CU, the register file's limit too), 64 KiB for complex128.
+// Measured on the 32-qubit headline circuits: complex64 tiles of 8192
+// amplitudes need fewer passes (44 against 53) but hold only four waves
+// per SIMD, and were slower overall; tiles of 16384 slower still.  The
+// batch kernel keeps 8192-amplitude complex64 tiles (whole circuits of up
+// to 13 qubits in one workgroup).
+int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 12 : 12; }
+int batch_tile_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
 
 // Register qubits per sweep: 16 complex64 or 8 complex128 amplitudes per
-// group (64 and 32 VGPRs), keeping two 512-thread workgroups per CU.
+// group (64 and 32 VGPRs); a 4096-amplitude tile then takes 256 or 512
+// threads.
 int sweep_width(int dtype) { return dtype == SV_C64 ? 4 : 3; }
 
 __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t base, uint32_t l) {
@@ -476,8 +482,11 @@ static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m,
                           hipStream_t s) {
     (void)hipFuncSetAttribute((const void *)k_tile<T, W, TWOQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 2048);
-    k_tile<T, W, TWOQ><<<grid, kTileThreads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles, direct);
+    // one workgroup per tile (measured faster than a capped grid looping
+    // over tiles), and one thread per register group
+    const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 30);
+    const unsigned threads = (unsigned)std::max(64, std::min(kTileThreads, (1 << m) >> W));
+    k_tile<T, W, TWOQ><<<grid, threads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles, direct);
 }
 
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
