@@ -489,6 +489,14 @@ static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m,
     k_tile<T, W, TWOQ><<<grid, threads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles, direct);
 }
 
+template <int W>
+static bool tile_staging_ok(int m, uint32_t direct) {
+    // staging the whole tile through LDS (a pass without direct first and
+    // last sweeps) moves it with kTileThreads threads
+    const int threads = std::max(64, std::min(kTileThreads, (1 << m) >> W));
+    return direct == (kDirectFirst | kDirectLast) || threads == kTileThreads;
+}
+
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
                        int n_sweeps, const char *dev_gates, bool two_qubit, uint32_t direct,
                        hipStream_t s) {
@@ -501,6 +509,7 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
     const int W = std::min(m, sweep_width(dtype));
 #define SV_TILE_CASE(WW, Q)                                                                        \
     if (W == WW && two_qubit == Q) {                                                               \
+        if (!tile_staging_ok<WW>(m, direct)) return hipErrorInvalidValue;                          \
         if (dtype == SV_C64)                                                                       \
             launch_tile_t<float, WW, Q>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,  \
                                         n_tiles, direct, lds, s);                                  \
