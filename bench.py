@@ -110,25 +110,84 @@ def read_stats(lib, handle):
             for i in range(n.value)}
 
 
-def cpu_baseline(n: int, circ, budget_s: float):
+def cpu_baseline(n: int, circ, budget_s: float, budget_1t_s: float):
     """FP64 oracle on the host: the first gates of the random circuit of the
-    n-qubit register, run until the time budget is spent."""
+    n-qubit register, run until the time budget is spent, on all host
+    threads (the reported value) and again on one thread."""
     import oracle as O
-    psi = O.basis_state(n, 0)
-    done_updates = 0
-    g_done = 0
-    t0 = time.perf_counter()
-    for g in circ.gates:
-        O.run_gates(n, [g], psi)
-        done_updates += (1 << n) >> len(g.controls)
-        g_done += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done_updates / dt, "unit": "updates/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {g_done} gates of the depth-20 random circuit on the {n}-qubit "
-                      f"state in FP64 complex ({dt:.1f} s)"}
+
+    def leg(budget):
+        psi = O.basis_state(n, 0)
+        done_updates = 0
+        g_done = 0
+        t0 = time.perf_counter()
+        for g in circ.gates:
+            O.run_gates(n, [g], psi)
+            done_updates += (1 << n) >> len(g.controls)
+            g_done += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return done_updates / (time.perf_counter() - t0), g_done, time.perf_counter() - t0
+
+    threads = O.num_threads()
+    v_all, g_all, dt_all = leg(budget_s)
+    O.set_num_threads(1)
+    try:
+        v_one, g_one, dt_one = leg(budget_1t_s)
+    finally:
+        O.set_num_threads(0)
+    return {"value": v_all, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {g_all} gates of the depth-20 random circuit on the {n}-qubit "
+                      f"state in FP64 complex ({dt_all:.1f} s, {threads} threads)",
+            "one_thread": {"value": v_one, "unit": "updates/s", "cores": 1,
+                           "sample": f"first {g_one} gates of the same circuit ({dt_one:.1f} s)"}}
+
+
+def target_bucket(lo: int) -> str:
+    """Bucket of a launch's lowest stride qubit (the target of a one-qubit
+    gate, the lowest qubit of a phase gate's subspace mask)."""
+    for a, b in ((0, 0), (1, 6), (7, 12), (13, 19), (20, 25), (26, 63)):
+        if a <= lo <= b:
+            return f"q{a}" if a == b else f"q{a}-{b}"
+    return "q?"
+
+
+def per_gate_breakdown(regs, lib, sv, _lib):
+    """Alg. 1 as the paper runs it, one launch per gate (sv_run in per-gate
+    mode, one gate per call) over the headline circuits of every register,
+    untimed: each launch's kernel time from the library's HIP events,
+    grouped by kernel and by the gate's lowest stride qubit.  GB/s counts the
+    launch's algorithmic bytes (2 s N / 2^controls; phase gates touch only
+    their subspace)."""
+    out = {}
+    for r in regs:
+        h = r["state"].handle
+        _lib.check(lib.sv_set_basis(h, r["qft"].basis))
+        _lib.check(lib.sv_timing(h, 1))
+        agg = {}
+        for key, c in (("ops_qft", r["qft"]), ("ops_rnd", r["rnd"])):
+            ops = r[key]
+            for i, g in enumerate(c.gates):
+                _lib.check(lib.sv_run(h, sv._opptr(ops[i:i + 1]), 1, None, 0, sv.SV_RUN_PER_GATE))
+                per = read_stats(lib, h)
+                phase = g.name in ("Z", "S", "T", "U1")
+                lo = min((*g.targets, *g.controls)) if phase else min(g.targets)
+                for kname, (cnt, ms, by, _fl) in per.items():
+                    a = agg.setdefault(kname, {}).setdefault(target_bucket(lo), [0, 0.0, 0.0])
+                    a[0] += cnt
+                    a[1] += ms
+                    a[2] += by
+        _lib.check(lib.sv_timing(h, 0))
+        reg = {}
+        for kname, buckets in agg.items():
+            tot = [sum(v[i] for v in buckets.values()) for i in range(3)]
+            reg[kname] = {"all": {"launches": tot[0], "avg_ms": round(tot[1] / tot[0], 4),
+                                  "GBps": round(tot[2] / (tot[1] * 1e-3) / 1e9, 1)},
+                          **{b: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4),
+                                 "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1)}
+                             for b, v in sorted(buckets.items())}}
+        out[f"{r['n']}q_{r['dtype']}"] = reg
+    return out
 
 
 def bench_fused(args, regs, lib, sv, _lib, torch):
@@ -402,6 +461,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="tiled", choices=["tiled", "per_gate"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds-1t", type=float, default=8.0,
+                    help="time budget of the one-thread oracle leg")
+    ap.add_argument("--no-seeds", action="store_true", help="skip the seed 1 and 2 runs")
+    ap.add_argument("--no-per-gate", action="store_true",
+                    help="skip the one-launch-per-gate breakdown by kernel and target")
     ap.add_argument("--cpu-qubits", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
@@ -510,6 +574,38 @@ def main():
             "norm": r["norm"], "z0": r["z0"],
         }
 
+    # the same step at the other seeds of the workload (short runs)
+    seeds = {str(args.seed): value}
+    if not args.no_seeds:
+        for sd in (1, 2):
+            if sd == args.seed:
+                continue
+            alt = []
+            for r in regs:
+                q2, r2 = C.config1(r["n"], sd)
+                alt.append((r, q2, r2, sv.ops_from_gates(q2.gates), sv.ops_from_gates(r2.gates)))
+
+            def step_seed():
+                for r, q2, r2, oq, orr in alt:
+                    h = r["state"].handle
+                    _lib.check(lib.sv_set_basis(h, q2.basis))
+                    _lib.check(lib.sv_run(h, sv._opptr(oq), len(q2.gates), None, 0, mode))
+                    _lib.check(lib.sv_run(h, sv._opptr(orr), len(r2.gates), None, 0, mode))
+                    _lib.check(lib.sv_probabilities(h, ctypes.c_void_p(r["probs"].data_ptr()),
+                                                    ctypes.byref(norm)))
+                    _lib.check(lib.sv_expectation(h, 1, zmask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                                  zcoef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                  ctypes.byref(ez)))
+            step_seed()
+            ns = max(1, min(3, args.steps))
+            dts = timed(step_seed, ns, torch)
+            ups = sum(updates(q2) + updates(r2) for _r, q2, r2, _a, _b in alt)
+            seeds[str(sd)] = ups * ns / dts
+
+    per_gate = None
+    if not args.no_per_gate and mode == sv.SV_RUN_TILED:
+        per_gate = per_gate_breakdown(regs, lib, sv, _lib)
+
     fused = None
     if not args.no_fused:
         same = bench_fused(args, regs, lib, sv, _lib, torch)
@@ -523,7 +619,7 @@ def main():
     if not args.no_cpu:
         n_cpu = args.cpu_qubits
         rnd = C.random_circuit(n_cpu, 20, args.seed + 1000, "X", n_cpu // 2)
-        cpu = cpu_baseline(n_cpu, rnd, args.cpu_seconds)
+        cpu = cpu_baseline(n_cpu, rnd, args.cpu_seconds, args.cpu_seconds_1t)
 
     dts = sorted({r["dtype"] for r in regs})
     out = {
@@ -546,6 +642,8 @@ def main():
         "hbm_roofline_frac_effective": round(total_plain_bytes / elapsed / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "seeds": seeds,
+        "per_gate": per_gate,
         "fused": fused,
         "breakdown": breakdown,
     }

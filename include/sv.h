@@ -147,9 +147,14 @@ int sv_apply_fused(sv_handle h, int k, const int *qubits, const double *U, int p
  * write) and, if host_norm is not NULL, the FP64 sum of all p_x. */
 int sv_probabilities(sv_handle h, void *dev_out, double *host_norm);
 
-/* <psi| sum_j coeffs[j] Z^{z_masks[j]} |psi> accumulated in FP64, where
- * Z^m is the product of Pauli Z on the qubits of mask m (eigenvalue
- * (-1)^popcount(x & m) on |x>).  1 <= n_terms <= 64. */
+/* Sec. 1.3.3 (measurement in the computational basis: outcome x has
+ * probability |psi_x|^2): the expectation of a diagonal observable,
+ * <psi| sum_j coeffs[j] Z^{z_masks[j]} |psi> = sum_x |psi_x|^2 h(x) with
+ * h(x) = sum_j coeffs[j] (-1)^popcount(x & z_masks[j]), accumulated in FP64;
+ * Z^m is the product of Pauli Z on the qubits of mask m.  z_masks and coeffs
+ * are n_terms host values (1 <= n_terms <= 64); *host_out (host) receives
+ * the result and the call waits for it.  SV_EINVAL for NULL pointers, a
+ * term count out of range or mask bits >= n. */
 int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const double *coeffs,
                    double *host_out);
 

@@ -78,12 +78,18 @@ def lib():
                                  ctypes.POINTER(ctypes.c_uint64)]
         L.oc_measure.restype = ctypes.c_double
         L.oc_num_threads.restype = ctypes.c_int
+        L.oc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().oc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Host threads of the following oracle calls (t < 1: the default)."""
+    lib().oc_set_num_threads(int(t))
 
 
 class _Packed:

@@ -27,6 +27,18 @@ int oc_num_threads(void) {
 #endif
 }
 
+/* Host threads of the calls that follow (the host baseline is timed on one
+ * thread and on all of them); t < 1 restores the default. */
+void oc_set_num_threads(int t) {
+#ifdef _OPENMP
+    static int dflt = 0;
+    if (!dflt) dflt = omp_get_max_threads();
+    omp_set_num_threads(t < 1 ? dflt : t);
+#else
+    (void)t;
+#endif
+}
+
 /* Sec. 2.1: a register starts in a basis state; all amplitude on index x. */
 void oc_init_basis(int n, uint64_t x, cplx *psi) {
     const uint64_t dim = 1ULL << n;

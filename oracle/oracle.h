@@ -105,6 +105,7 @@ double oc_measure(int n, double complex *psi, uint64_t mask, double u, uint64_t 
 
 /* Number of OpenMP threads the oracle's loops use. */
 int oc_num_threads(void);
+void oc_set_num_threads(int t);
 
 #ifdef __cplusplus
 }

@@ -29,20 +29,25 @@ class ExpectationCircuit:
         self.mode = mode
         self.psi = State(n_qubits, dtype)
         self.lam = State(n_qubits, dtype)
-        self._fresh = False
+        # parameters whose circuit output psi currently holds (None: psi does
+        # not hold a circuit output)
+        self._psi_params = None
 
     def loss(self, params) -> float:
         """<H> at the given parameters (leaves psi holding the circuit output)."""
+        params = np.array(params, np.float64)  # a copy: the caller may change its array
         sv_set_basis(self.psi.handle, 0)
-        sv_run(self.psi.handle, self.gates, np.asarray(params, np.float64), self.mode)
-        self._fresh = True
+        sv_run(self.psi.handle, self.gates, params, self.mode)
+        self._psi_params = params
         return sv_expectation(self.psi.handle, self.z_masks, self.coeffs)
 
     def loss_and_grad(self, params):
+        """(loss, gradient) at params; the forward circuit is run again unless
+        psi already holds its output for exactly these parameters."""
         params = np.asarray(params, np.float64)
-        if not self._fresh:
+        if self._psi_params is None or not np.array_equal(self._psi_params, params):
             self.loss(params)
-        self._fresh = False  # the sweep leaves psi at the input state
+        self._psi_params = None  # the sweep leaves psi at the input state
         return sv_adjoint_grad(self.psi.handle, self.lam.handle, self.gates, params,
                                self.z_masks, self.coeffs)
 
@@ -65,10 +70,9 @@ def _make_function():
 
         @staticmethod
         def backward(ctx, grad_out):
-            circuit = ctx.circuit
-            if not circuit._fresh:
-                circuit.loss(ctx.params)
-            _, grad = circuit.loss_and_grad(ctx.params)
+            # loss_and_grad reruns the forward circuit when psi holds another
+            # parameter vector's output (e.g. a later forward call)
+            _, grad = ctx.circuit.loss_and_grad(ctx.params)
             g = torch.from_numpy(grad).to(ctx.device) * grad_out.to(torch.float64)
             return g, None
 

@@ -137,9 +137,9 @@ hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int
 // Both vectors of a tile sit in LDS; each register sweep loads the same group
 // of psi and lam and undoes the sweep's gates on both.  A parametrised gate
 // is preceded by a probe record that adds the group's share of
-// Im <lam| M |psi> to the gate's slot (wave reduction, then one LDS atomic
-// per wave).  The slot sums of a
-// workgroup cover all its tiles and are written once at the end.
+// Im <lam| M |psi> to the gate's slot (wave reduction, then lane 0 adds it
+// to its wave's row of slots).  The slot sums of a workgroup cover all its
+// tiles and are written once at the end.
 int adjoint_tile_qubits(int dtype) { return dtype == SV_C64 ? 12 : 11; } // 2 x 32 KiB of LDS
 
 template <typename T, int W, int P>
@@ -183,8 +183,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
     const uint32_t tsize = 1u << m;
     cpx<T> *lp = reinterpret_cast<cpx<T> *>(lds_raw);
     cpx<T> *ll = lp + tsize;
-    __shared__ double slot_acc[kMaxAdjSlots];
-    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) slot_acc[i] = 0.0;
+    // one row of slot sums per wave, written only by that wave's lane 0 (no
+    // atomics): the workgroup's sums are then formed in a fixed order and the
+    // gradient is the same bit for bit on every run
+    constexpr int kWaves = kAdjThreads / 64;
+    __shared__ double slot_acc[kWaves][kMaxAdjSlots];
+    for (int i = threadIdx.x; i < kWaves * kMaxAdjSlots; i += blockDim.x) (&slot_acc[0][0])[i] = 0.0;
+    __syncthreads();
     const uint32_t n_groups = tsize >> W;
     cpx<T> *ps = reinterpret_cast<cpx<T> *>(psi);
     cpx<T> *ls = reinterpret_cast<cpx<T> *>(lam);
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                         if ((base & G.cout) != G.cout) continue; // uniform
                         const double mine = act ? probe_gate<T, W>(v, w, gb, G) : 0.0;
                         const double c = wave_sum_d(mine);
-                        if ((threadIdx.x & 63) == 0) atomicAdd(&slot_acc[G.b1], c);
+                        if ((threadIdx.x & 63) == 0) slot_acc[threadIdx.x >> 6][G.b1] += c;
                     } else {
                         // adjoint passes carry no gathered phases (their
                         // probes read the amplitudes between gates)
@@ -271,8 +276,12 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < n_slots; i += blockDim.x)
-        partials[(size_t)(slot0 + i) * gridDim.x + blockIdx.x] = slot_acc[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += slot_acc[w][i];
+        partials[(size_t)(slot0 + i) * gridDim.x + blockIdx.x] = t;
+    }
 }
 
 hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const TileSpec &spec,

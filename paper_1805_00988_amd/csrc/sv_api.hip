@@ -1606,6 +1606,12 @@ static void batch_release_program(sv_batch *b) {
 
 // Build, upload and capture the batch program for (tile_m, sweep_w, grid).
 static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
+    // the kernel is instantiated for sweeps of exactly sweep_w register
+    // qubits: a circuit narrower than that would have no register groups
+    const int wnarrow = *std::min_element(b->widths.begin(), b->widths.end());
+    if (sweep_w > wnarrow || sweep_w > tile_m)
+        return fail(SV_EINVAL, "sweep width " + std::to_string(sweep_w) + " exceeds the narrowest circuit (" +
+                                   std::to_string(wnarrow) + " qubits) or the tile");
     SV_HIP(hipStreamSynchronize(b->stream));
     batch_release_program(b);
     const bool keep = (b->flags & SV_BATCH_KEEP_STATES) != 0;
@@ -2339,9 +2345,12 @@ int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *g
     SV_HIP(hipEventCreate(&e0));
     SV_HIP(hipEventCreate(&e1));
     int rc = SV_OK;
+    const int wnarrow = *std::min_element(b->widths.begin(), b->widths.end());
     for (int wi = 0; wi < 2 && !rc; ++wi)
         for (int mi = 0; mi < 3 && !rc; ++mi)
             for (int gi = 0; gi < 2 && !rc; ++gi) {
+                // sweeps wider than the narrowest circuit are not candidates
+                if (ws[wi] > wnarrow) continue;
                 if ((rc = batch_prepare(b, ms[mi], ws[wi], gs[gi]))) break;
                 float ms_run = 0.0f;
                 hipError_t e = hipEventRecord(e0, b->stream);

@@ -113,6 +113,31 @@ def test_batch_autotuner_keeps_results():
     b.close()
 
 
+def test_batch_autotuner_complex128_narrow_circuits():
+    """The tuner's sweep-width candidates never exceed the narrowest circuit:
+    a complex128 batch holding 3-qubit circuits keeps correct results for
+    whatever (tile, sweep width, grid) it picks."""
+    rng = np.random.default_rng(11)
+    circs = [C.hea_circuit(3, 3, seed=i, entangler="ladder").bound() for i in range(6)]
+    circs += [C.random_circuit(int(rng.integers(3, 15)), 4, seed=50 + i, entangler="X") for i in range(18)]
+    b = sv.Batch(circs, "c128", z_mask=1)
+    choice = b.tune(reps=1)
+    assert choice["sweep_width"] == 3
+    b.run()
+    z = b.results()
+    for i, c in enumerate(circs):
+        ref = z_of(O.run(c), c.n, 1)
+        assert abs(z[i] - ref) <= 1e-12, (i, c.n, z[i], ref)
+    b.close()
+
+
+def test_batch_rejects_sweep_wider_than_narrowest_circuit():
+    """A complex64 batch may not use 4-qubit sweeps with a 3-qubit circuit;
+    the C entry point refuses such circuits (widths below 4 for complex64)."""
+    with pytest.raises(sv.SVError):
+        sv.Batch([C.random_circuit(3, 2, 0), C.random_circuit(8, 2, 1)], "c64")
+
+
 def test_batched_workload_full_size_sampled():
     """4096 circuits, widths uniform in 10..20, 8 ladder-ansatz layers,
     complex64, one graph launch; <Z_0> of a sampled subset (including the

@@ -104,6 +104,35 @@ def test_multi_controlled_gates_tiled(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+def test_many_controls_streamed(dtype):
+    """Gates with 10 to 13 controls at 16 qubits, one launch per gate: the
+    streamed kernels enumerate at most 10 inserted bit positions (target and
+    controls) and test the remaining control bits per element.  General,
+    phase (subspace) and two-qubit gates, controls above and below their
+    targets, against the oracle."""
+    n = 16
+    rng = np.random.default_rng(77)
+    gates = [C.Gate("H", (q,)) for q in range(n)]
+    for i in range(12):
+        nc = 10 + i % 4
+        two = i % 3 == 2
+        qs = [int(q) for q in rng.choice(n, size=nc + (2 if two else 1), replace=False)]
+        tg = tuple(qs[:2] if two else qs[:1])
+        ctrl = tuple(qs[len(tg):])
+        if two:
+            gates.append(C.Gate("U", tg, ctrl, 0.0, -1, C.random_unitary(4, rng)))
+        elif i % 3 == 1:
+            gates.append(C.Gate("U1", tg, ctrl, float(rng.uniform(0, 6.28))))
+        else:
+            gates.append(C.Gate("U", tg, ctrl, 0.0, -1, C.random_unitary(2, rng)))
+    got, ref = run_both(n, dtype, gates, seed=78, mode=sv.SV_RUN_PER_GATE)
+    assert_state_close(got, ref, dtype, len(gates))
+    # the controls must have acted: the controlled part changes the state
+    plain = O.run_gates(n, gates[:n], oracle_input(random_state(n, 78), dtype))
+    assert np.max(np.abs(ref - plain)) > 1e-6
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_two_qubit_gates_all_pairs(dtype):
     n = 6
     rng = np.random.default_rng(8)
@@ -331,3 +360,21 @@ def test_invalid_arguments_leave_state_unchanged(dtype):
     with pytest.raises(sv.SVError):
         st.set_basis(1 << n)
     np.testing.assert_array_equal(st.numpy(), before)
+
+
+def test_alloc_beyond_device_memory_is_enomem():
+    """A 36-qubit complex64 register (512 GiB) exceeds the device: sv_alloc
+    returns SV_ENOMEM before allocating anything, and the device stays usable."""
+    import ctypes
+    from paper_1805_00988_amd import _lib
+    lib = _lib.load()
+    free0, _ = torch.cuda.mem_get_info()
+    h = ctypes.c_void_p()
+    rc = lib.sv_alloc(36, sv.SV_C64, None, None, ctypes.byref(h))
+    assert rc == -2, rc  # SV_ENOMEM
+    assert not h.value
+    assert "memory" in lib.sv_last_error().decode().lower()
+    free1, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free0) < (64 << 20)
+    st = sv.State(10, "c64")
+    assert abs(st.probabilities() - 1.0) < 1e-6
