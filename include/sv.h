@@ -158,6 +158,26 @@ int sv_probabilities(sv_handle h, void *dev_out, double *host_norm);
 int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const double *coeffs,
                    double *host_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the
+ * expectation of sv_expectation, computed by the same kernels, on a caller's
+ * state without a handle, without any allocation and without waiting.
+ * dev_amps: device pointer to the 2^n_qubits amplitudes (16-byte aligned,
+ * layout as for every entry point); z_masks, coeffs: n_terms host values
+ * (1 <= n_terms <= 64), read before the call returns; dev_out: device
+ * pointer to one double that receives the FP64 result when the work on
+ * hip_stream (NULL = null stream) reaches it.  The partial sums live in a
+ * static device array of the library (8 KiB per device, held until the
+ * process ends; any state size fits it, since the reduction uses at most
+ * 1024 workgroups): calls that overlap on one device race, calls ordered on
+ * one stream do not.  The device current at the call must be the one
+ * holding dev_amps.  SV_EINVAL for NULL or misaligned pointers, n_qubits
+ * outside [1, 40], an unknown dtype, n_terms outside [1, 64] or mask bits
+ * >= n_qubits; SV_EDEVICE if the launch fails. */
+int sv_expectation_noalloc(const void *dev_amps, int n_qubits, int dtype, int n_terms,
+                           const uint64_t *z_masks, const double *coeffs, double *dev_out,
+                           void *hip_stream);
+
 /* Run a gate list on the state.  params (n_params doubles, may be NULL when
  * no op has param_index >= 0) supplies the angles of parametrised ops.
  * mode SV_RUN_PER_GATE launches one kernel per gate; SV_RUN_TILED lets the

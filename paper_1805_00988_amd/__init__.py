@@ -19,7 +19,7 @@ from ._lib import (GATE_KINDS, SV_C64, SV_C128, SV_PREC_FP32, SV_PREC_NATIVE,
                    SV_PREC_SPLIT_BF16, SV_RUN_PER_GATE, SV_RUN_TILED, SVError, sv_op)
 
 __all__ = ["State", "sv_alloc", "sv_free", "sv_set_basis", "sv_apply_gate", "sv_apply_fused",
-           "sv_probabilities", "sv_expectation", "sv_run", "sv_fuse", "sv_run_fused",
+           "sv_probabilities", "sv_expectation", "sv_expectation_noalloc", "sv_run", "sv_fuse", "sv_run_fused",
            "sv_adjoint_grad", "sv_state_bytes", "ops_from_gates", "SV_C64", "SV_C128",
            "SV_PREC_NATIVE", "SV_PREC_FP32", "SV_PREC_SPLIT_BF16", "SV_RUN_PER_GATE",
            "SV_RUN_TILED", "SVError", "Batch"]
@@ -117,6 +117,19 @@ def sv_expectation(h, z_masks: Sequence[int], coeffs: Sequence[float]) -> float:
     out = ctypes.c_double()
     _lib.check(_lib.load().sv_expectation(h, len(m), _u64ptr(m), _dptr(c), ctypes.byref(out)))
     return out.value
+
+
+def sv_expectation_noalloc(amps, n_qubits: int, z_masks: Sequence[int], coeffs: Sequence[float],
+                           out, stream=None) -> None:
+    """Expectation of a caller's state (CUDA complex64/complex128 tensor of
+    2^n elements) written to ``out`` (a CUDA float64 tensor, element 0) on the
+    stream, with no allocation and no host wait."""
+    m = np.ascontiguousarray(z_masks, dtype=np.uint64)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    s = stream if stream is not None else _current_stream()
+    _lib.check(_lib.load().sv_expectation_noalloc(ctypes.c_void_p(amps.data_ptr()), int(n_qubits),
+                                                 _dtype_code(amps.dtype), len(m), _u64ptr(m), _dptr(c),
+                                                 ctypes.c_void_p(out.data_ptr()), s))
 
 
 def sv_marginals(h, mask: int) -> np.ndarray:

@@ -22,7 +22,7 @@ GATE_KINDS = {"H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6,
 
 EXPORTED = ("sv_state_bytes", "sv_alloc", "sv_free", "sv_set_basis", "sv_set_stream", "sv_sync",
             "sv_data", "sv_apply_gate", "sv_apply_fused", "sv_probabilities", "sv_expectation",
-            "sv_marginals", "sv_collapse", "sv_measure", "sv_sample",
+            "sv_expectation_noalloc", "sv_marginals", "sv_collapse", "sv_measure", "sv_sample",
             "sv_run", "sv_fuse", "sv_run_fused", "sv_adjoint_grad", "sv_batch_create",
             "sv_batch_run", "sv_batch_results", "sv_batch_output", "sv_batch_state",
             "sv_batch_tune", "sv_batch_free", "sv_timing", "sv_timing_read", "sv_last_error",
@@ -71,6 +71,7 @@ _PROTOS = {
     "sv_apply_fused": (_I, [_P, _I, _IP, _DP, _I]),
     "sv_probabilities": (_I, [_P, _P, _DP]),
     "sv_expectation": (_I, [_P, _I, _U64P, _DP, _DP]),
+    "sv_expectation_noalloc": (_I, [_P, _I, _I, _I, _U64P, _DP, _P, _P]),
     "sv_marginals": (_I, [_P, _U64, _DP]),
     "sv_collapse": (_I, [_P, _U64, _U64, _DP]),
     "sv_measure": (_I, [_P, _U64, ctypes.c_double, _U64P, _DP]),

@@ -8,6 +8,7 @@
 #include "sv_internal.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace sv {
 
@@ -161,6 +162,48 @@ hipError_t launch_expectation(const void *amps, int n, int dtype, int n_terms,
     }
     k_sum_partials<<<dim3(1), dim3(kRedThreads), 0, s>>>(dev_partials, (int)grid, dev_total);
     return hipGetLastError();
+}
+
+// ------------------------------------------- reduction without allocation
+// Partial sums of sv_expectation_noalloc: one FP64 per reduction workgroup
+// (kReduceBlocks of them, 8 KiB).  Every device the library runs on holds its
+// own copy until the process ends.  In host code the array's name only
+// stands for the symbol: its device address, which differs per device, is
+// taken once per device with hipGetSymbolAddress and used for every kernel
+// argument.  Calls on one device share the array, so calls that overlap on
+// one device (two streams) race; calls ordered on one stream do not.  Every
+// launch writes each partial it later reads, so nothing needs clearing.
+static __device__ __align__(256) double scratch[kReduceBlocks];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_addr[kMaxScratchDevices] = {};
+
+static hipError_t scratch_address(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_expectation_static(const void *amps, int n, int dtype, int n_terms,
+                                     const uint64_t *masks, const double *coeffs, double *dev_total,
+                                     hipStream_t s) {
+    double *partials = nullptr;
+    const hipError_t e = scratch_address(&partials);
+    if (e != hipSuccess) return e;
+    // red_grid never exceeds the partial count it is given: the array's size
+    static_assert(sizeof(scratch) == kReduceBlocks * sizeof(double), "one partial per workgroup");
+    return launch_expectation(amps, n, dtype, n_terms, masks, coeffs, partials, kReduceBlocks, dev_total, s);
 }
 
 } // namespace sv

@@ -1854,6 +1854,22 @@ int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const doub
     return SV_OK;
 }
 
+int sv_expectation_noalloc(const void *dev_amps, int n_qubits, int dtype, int n_terms, const uint64_t *z_masks,
+                           const double *coeffs, double *dev_out, void *hip_stream) {
+    if (!dev_amps || !dev_out || !z_masks || !coeffs) return fail(SV_EINVAL, "NULL argument");
+    if (n_qubits < 1 || n_qubits > 40) return fail(SV_EINVAL, "n_qubits must be in [1, 40]");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    if (reinterpret_cast<uintptr_t>(dev_amps) & 15u) return fail(SV_EINVAL, "dev_amps must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(dev_out) & 7u) return fail(SV_EINVAL, "dev_out must be 8-byte aligned");
+    if (n_terms < 1 || n_terms > kMaxTerms)
+        return fail(SV_EINVAL, "n_terms must be in [1, 64] (the terms travel as kernel arguments)");
+    for (int j = 0; j < n_terms; ++j)
+        if (n_qubits < 64 && (z_masks[j] >> n_qubits) != 0) return fail(SV_EINVAL, "Z mask has bits >= n");
+    SV_HIP(launch_expectation_static(dev_amps, n_qubits, dtype, n_terms, z_masks, coeffs, dev_out,
+                                     (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
 // ============================================================ measurement
 static int measure_positions(const sv_state *h, uint64_t mask, MeasurePos *mp) {
     if (mask == 0) return fail(SV_EINVAL, "empty qubit mask");

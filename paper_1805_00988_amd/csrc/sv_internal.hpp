@@ -222,6 +222,12 @@ hipError_t launch_expectation(const void *amps, int n, int dtype, int n_terms,
                               const uint64_t *masks, const double *coeffs, double *dev_partials,
                               int n_partials, double *dev_total, hipStream_t s);
 constexpr int kReduceBlocks = 1024;
+// sv_expectation on a caller's state with its partial sums in the library's
+// static device array (no allocation); the same kernels and grid as
+// launch_expectation with kReduceBlocks partials
+hipError_t launch_expectation_static(const void *amps, int n, int dtype, int n_terms,
+                                     const uint64_t *masks, const double *coeffs, double *dev_total,
+                                     hipStream_t s);
 
 // ------------------------------------------------------------- batches
 struct BatchCircuit {
