@@ -190,29 +190,45 @@ def per_gate_breakdown(regs, lib, sv, _lib):
     return out
 
 
+PREC_NAMES = {0: "native", 1: "fp32", 2: "bf16x3"}
+
+
 def bench_fused(args, regs, lib, sv, _lib, torch):
-    """The same workload through the fused path: greedy blocks of up to
-    fuse-k qubits in tile passes (matrix cores for complex64, FP64 vector
-    ALUs for complex128).  Fidelity is taken against the plain path's final
+    """The same workload through the fused path, with the fused path's
+    autotuner (sv_fused_tune) choosing, per register and circuit, between
+    plain tile passes and fused passes of at most 4 or 5 qubits in each
+    allowed arithmetic (complex64: FP32 and split-BF16 matrix cores;
+    complex128: FP64).  Fidelity is taken against the plain path's final
     state of the same register."""
-    prec_c64 = sv.SV_PREC_SPLIT_BF16 if args.fused_prec == "bf16x3" else sv.SV_PREC_FP32
     plain_final = {}
     for r in regs:  # reference: plain final state of this step's input
         plain_final[r["n"]] = r["state"].amps.clone()
     nb = ctypes.c_int()
     norm = ctypes.c_double()
+    kk, pp, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    choice = {}
+    for r in regs:  # tune each circuit from the state it starts from
+        h = r["state"].handle
+        _lib.check(lib.sv_set_basis(h, r["qft"].basis))
+        for key, c in (("ops_qft", r["qft"]), ("ops_rnd", r["rnd"])):
+            _lib.check(lib.sv_fused_tune(h, sv._opptr(r[key]), len(c.gates), None, 0, args.fuse_k, 0b111, 1,
+                                         ctypes.byref(kk), ctypes.byref(pp), ctypes.byref(ms)))
+            choice[(r["n"], key)] = (kk.value, pp.value)
+            _lib.check(lib.sv_run(h, sv._opptr(r[key]), len(c.gates), None, 0, sv.SV_RUN_TILED))
 
     def fstep():
         for r in regs:
             h = r["state"].handle
-            prec = prec_c64 if r["dtype"] == "c64" else sv.SV_PREC_NATIVE
             _lib.check(lib.sv_set_basis(h, r["qft"].basis))
             blocks = 0
-            kmax = args.fuse_k if r["dtype"] == "c64" else min(args.fuse_k, 4)
             for key, c in (("ops_qft", r["qft"]), ("ops_rnd", r["rnd"])):
-                _lib.check(lib.sv_run_fused(h, sv._opptr(r[key]), len(c.gates), None, 0, kmax, prec,
-                                            ctypes.byref(nb)))
-                blocks += nb.value
+                k, prec = choice[(r["n"], key)]
+                if k == 0:
+                    _lib.check(lib.sv_run(h, sv._opptr(r[key]), len(c.gates), None, 0, sv.SV_RUN_TILED))
+                else:
+                    _lib.check(lib.sv_run_fused(h, sv._opptr(r[key]), len(c.gates), None, 0, k, prec,
+                                                ctypes.byref(nb)))
+                    blocks += nb.value
             _lib.check(lib.sv_probabilities(h, ctypes.c_void_p(r["probs"].data_ptr()), ctypes.byref(norm)))
             r["fused_blocks"], r["fused_norm"] = blocks, norm.value
 
@@ -226,9 +242,9 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
         print(f"# fused step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = {"workload": "the same QFT + random circuit, fused", "prec_complex64": args.fused_prec,
-           "prec_complex128": "fp64 matrix cores", "k_max": args.fuse_k, "k_max_complex128": min(args.fuse_k, 4),
-           "ms_per_step": dt / args.steps * 1e3, "registers": {}}
+    out = {"workload": "the same QFT + random circuit through the fused path, configuration per circuit "
+                       "chosen by the autotuner (sv_fused_tune)",
+           "k_max": args.fuse_k, "ms_per_step": dt / args.steps * 1e3, "registers": {}}
     total = 0
     for r in regs:
         per = read_stats(lib, r["state"].handle)
@@ -243,8 +259,11 @@ def bench_fused(args, regs, lib, sv, _lib, torch):
             nb2 += float(torch.vdot(bc, bc).real.item())
         fid = abs(ov) ** 2 / (na * nb2)
         total += r["updates"]
-        fk = per.get("fused_block", (1, 0.0, 0.0, 0.0))
+        fk = per.get("fused_block", (0, 0.0, 0.0, 0.0))
         out["registers"][f"{r['n']}q_{r['dtype']}"] = {
+            "choice": {name: ("plain" if choice[(r["n"], key)][0] == 0 else
+                              f"k{choice[(r['n'], key)][0]}_{PREC_NAMES[choice[(r['n'], key)][1]]}")
+                       for name, key in (("qft", "ops_qft"), ("random", "ops_rnd"))},
             "blocks_per_step": r["fused_blocks"], "norm": r["fused_norm"],
             "fidelity_vs_plain": fid,
             "fused_pass_launches": fk[0] // args.steps,
@@ -317,12 +336,19 @@ def bench_fusion(n, seed, steps, warmup, torch):
                       "pass_avg_ms": round(kms / kc, 3) if kc else None,
                       "pass_GBps": round(kby / (kms * 1e-3) / 1e9, 1) if kms > 0 else None,
                       "infidelity_vs_c128": 1.0 - fid, "max_abs_err_vs_c128": mx}
+    _lib.check(lib.sv_set_basis(st.handle, 0))
+    kk, pp, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _lib.check(lib.sv_fused_tune(st.handle, sv._opptr(ops), len(circ), None, 0, 5, 0b111, 1, ctypes.byref(kk),
+                                 ctypes.byref(pp), ctypes.byref(ms)))
+    tuned = {"choice": "plain" if kk.value == 0 else f"k{kk.value}_{PREC_NAMES[pp.value]}",
+             "tuner_ms": round(ms.value, 3)}
     del st, ref
     fused = {k: v for k, v in res.items() if k != "plain"}
     best = max(fused, key=lambda k: fused[k]["updates_per_s"])
     return {"workload": f"{n}-qubit random circuit, depth 40 (1q layer + {n // 2} CZ), complex64, seed {seed}",
             "gates": len(circ), "updates_per_step": circ.updates(), "variants": res, "best_fused": best,
-            "speedup_best_fused_vs_plain": res[best]["updates_per_s"] / res["plain"]["updates_per_s"]}
+            "speedup_best_fused_vs_plain": res[best]["updates_per_s"] / res["plain"]["updates_per_s"],
+            "autotuner": tuned}
 
 
 def timed(fn, steps, torch):
@@ -426,6 +452,20 @@ def other_workload(args):
                 z_plain[i] = ez.value
         plain_all()
         dtp = timed(plain_all, args.steps, torch)
+        # tail: each width's first circuit alone in a batch of one (one
+        # workgroup walks it), with the tuned tile size and sweep width
+        tail = {}
+        for w in sorted({c.n for c in circs}):
+            one = sv.Batch([next(c for c in circs if c.n == w)], "c64", z_mask=1)
+            _lib.check(lib.sv_batch_tune(one.handle, 1, None, None, None, None))
+            one.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                one.run()
+            torch.cuda.synchronize()
+            tail[str(w)] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+            one.close()
         out.update({"value": ups * args.steps / dt2, "dtype": "f32",
                     "config": {"workload": "4096 ladder-ansatz circuits, widths 10..20, 8 layers, complex64, "
                                            "one graph launch, <Z_0> per circuit"},
@@ -435,7 +475,8 @@ def other_workload(args):
                     "plain": {"ms_per_step": dtp / args.steps * 1e3, "updates_per_s": ups * args.steps / dtp,
                               "how": "per circuit: sv_set_basis, sv_run (tile passes), sv_expectation",
                               "max_abs_diff_z0_vs_batch": float(np.max(np.abs(z_plain - z_batch)))},
-                    "speedup_vs_plain": dtp / dt2})
+                    "speedup_vs_plain": dtp / dt2,
+                    "one_circuit_alone_ms_by_width": tail})
     elif args.workload == "qft_sweep":
         out.update(qft_sweep(args, torch, sv))
     else:
@@ -469,9 +510,7 @@ def main():
     ap.add_argument("--cpu-qubits", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
-    ap.add_argument("--fuse-k", type=int, default=5)
-    ap.add_argument("--fused-prec", default="bf16x3", choices=["fp32", "bf16x3"],
-                    help="matrix-core arithmetic of complex64 fused blocks")
+    ap.add_argument("--fuse-k", type=int, default=5, help="widest fused block the autotuner may choose")
     ap.add_argument("--workload", default="plain-at-scale",
                     choices=["plain-at-scale", "fusion", "batch", "adjoint", "qft_sweep"],
                     help="plain-at-scale (default headline line); the others time the "

@@ -167,9 +167,9 @@ int sv_expectation(sv_handle h, int n_terms, const uint64_t *z_masks, const doub
  * (1 <= n_terms <= 64), read before the call returns; dev_out: device
  * pointer to one double that receives the FP64 result when the work on
  * hip_stream (NULL = null stream) reaches it.  The partial sums live in a
- * static device array of the library (8 KiB per device, held until the
+ * static device array of the library (64 KiB per device, held until the
  * process ends; any state size fits it, since the reduction uses at most
- * 1024 workgroups): calls that overlap on one device race, calls ordered on
+ * 8192 workgroups): calls that overlap on one device race, calls ordered on
  * one stream do not.  The device current at the call must be the one
  * holding dev_amps.  SV_EINVAL for NULL or misaligned pointers, n_qubits
  * outside [1, 40], an unknown dtype, n_terms outside [1, 64] or mask bits
@@ -203,16 +203,36 @@ int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int
  * into passes whose qubits (targets and controls) fit one LDS tile, then the
  * gates of each pass are fused as by sv_fuse into blocks of at most k_max
  * qubits, and every block of a pass is applied, as by sv_apply_fused(prec),
- * during a single read and write of the state.  A diagonal gate of at most
+ * during a single read and write of the state.  Per pass, a cost model
+ * (fitted to MI355X kernel times) picks the cheapest of: blocks of at most
+ * k_max qubits, blocks of at most 4 qubits (when k_max is 5), and the pass's
+ * gates applied one by one as register sweeps in the state's own precision
+ * (as sv_run does), so a pass never runs a fused form the model rates slower
+ * than the plain one.  A diagonal gate of at most
  * four qubits may keep qubits outside the tile: they are fixed within one
  * tile, so the block holding the gate carries one matrix per value of its
  * outside qubits (at most 16) and each tile uses its own.  Only a gate's
  * qubits inside the tile count towards k_max in a block; every gate must
  * still touch at most k_max qubits (SV_EINVAL).  *n_blocks_out (may be
- * NULL) receives the number of blocks applied.  Same result as sv_run up
+ * NULL) receives the number of blocks applied (passes run as plain sweeps
+ * add none).  Same result as sv_run up
  * to rounding (FP32 or split-BF16 products for prec != SV_PREC_NATIVE). */
 int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
                  int k_max, int prec, int *n_blocks_out);
+
+/* Autotuner of the fused path: runs the gate list once untimed and reps
+ * times timed (HIP events on the handle's stream) for each candidate, each
+ * run from the handle's present state, and reports the fastest: k = 0 for
+ * plain tile passes (sv_run, SV_RUN_TILED), else sv_run_fused with k_max
+ * = k in {4, 5} (k <= k_max, and no gate wider than k) and precision p with
+ * bit p of prec_mask set (complex64: SV_PREC_FP32, SV_PREC_SPLIT_BF16;
+ * complex128: SV_PREC_NATIVE).  *k_out, *prec_out receive the choice and
+ * *ms_out (may be NULL) its time per run.  The state is left as it was on
+ * entry; a temporary device copy of it is allocated for the duration
+ * (SV_ENOMEM if it does not fit).  Plain passes are always a candidate, so
+ * the choice is never slower than sv_run as measured. */
+int sv_fused_tune(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
+                  int k_max, int prec_mask, int reps, int *k_out, int *prec_out, double *ms_out);
 
 /* Sec. 1.3.3: outcome probabilities of measuring the k <= 6 qubits of mask
  * in the computational basis.  host_out[o] (2^k doubles, host) = sum of

@@ -19,7 +19,7 @@ from ._lib import (GATE_KINDS, SV_C64, SV_C128, SV_PREC_FP32, SV_PREC_NATIVE,
                    SV_PREC_SPLIT_BF16, SV_RUN_PER_GATE, SV_RUN_TILED, SVError, sv_op)
 
 __all__ = ["State", "sv_alloc", "sv_free", "sv_set_basis", "sv_apply_gate", "sv_apply_fused",
-           "sv_probabilities", "sv_expectation", "sv_expectation_noalloc", "sv_run", "sv_fuse", "sv_run_fused",
+           "sv_probabilities", "sv_expectation", "sv_expectation_noalloc", "sv_run", "sv_fuse", "sv_run_fused", "sv_fused_tune",
            "sv_adjoint_grad", "sv_state_bytes", "ops_from_gates", "SV_C64", "SV_C128",
            "SV_PREC_NATIVE", "SV_PREC_FP32", "SV_PREC_SPLIT_BF16", "SV_RUN_PER_GATE",
            "SV_RUN_TILED", "SVError", "Batch"]
@@ -241,6 +241,18 @@ def sv_run_fused(h, gates, k_max: int, prec: int, params=None) -> int:
     return nb.value
 
 
+def sv_fused_tune(h, gates, k_max: int = 5, prec_mask: int = 0b111, reps: int = 1, params=None) -> dict:
+    """Fastest of plain tile passes and fused passes (k in {4, 5} <= k_max,
+    precisions in prec_mask) measured on the handle's state, which is left
+    unchanged: {"k": 0 for plain, "prec": ..., "ms": ...}."""
+    ops = ops_from_gates(gates)
+    pp, n_p, keep = _params(params)
+    k, p, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _lib.check(_lib.load().sv_fused_tune(h, _opptr(ops), len(gates), pp, n_p, int(k_max), int(prec_mask),
+                                         int(reps), ctypes.byref(k), ctypes.byref(p), ctypes.byref(ms)))
+    return {"k": k.value, "prec": p.value, "ms": ms.value}
+
+
 def sv_adjoint_grad(h, lam, gates, params, z_masks, coeffs):
     ops = ops_from_gates(gates)
     p = np.ascontiguousarray(params, dtype=np.float64)
@@ -455,6 +467,10 @@ class State:
     def run_fused(self, gates, k_max: int = 5, prec: int = SV_PREC_FP32, params=None) -> int:
         self.flush()
         return sv_run_fused(self.handle, gates, k_max, prec, params)
+
+    def fused_tune(self, gates, k_max: int = 5, prec_mask: int = 0b111, reps: int = 1, params=None) -> dict:
+        self.flush()
+        return sv_fused_tune(self.handle, gates, k_max, prec_mask, reps, params)
 
     def probabilities(self, out=None) -> float:
         self.flush()

@@ -142,11 +142,39 @@ hipError_t launch_adjoint_init(const void *psi, void *lam, int n, int dtype, int
 // tiles and are written once at the end.
 int adjoint_tile_qubits(int dtype) { return dtype == SV_C64 ? 12 : 11; } // 2 x 32 KiB of LDS
 
-template <typename T, int W, int P>
+// Re(conj(y) z) in FP64
+template <typename T>
+__device__ __forceinline__ double re_conj_mul(cpx<T> y, cpx<T> z) {
+    return (double)y.re * (double)z.re + (double)y.im * (double)z.im;
+}
+
+// The pair (j, c = j | 2^P) of psi (v) and lam (w): Im(conj(w_j) z_0) +
+// Im(conj(w_c) z_1) with z = M (v_j, v_c).  For M = X: z = (v_c, v_j); Y:
+// (-i v_c, i v_j), so Im(conj(w) (+-i) v) = +-Re(conj(w) v); Z: (v_j, -v_c);
+// |1><1|: (0, v_c).
+template <typename T, int KIND>
+__device__ __forceinline__ double probe_pair(const cpx<T> &vj, const cpx<T> &vc, const cpx<T> &wj,
+                                             const cpx<T> &wc, const TileGate &G) {
+    if constexpr (KIND == SK_PROBE_X) {
+        return im_conj_mul(wj, vc) + im_conj_mul(wc, vj);
+    } else if constexpr (KIND == SK_PROBE_Y) {
+        return re_conj_mul(wc, vj) - re_conj_mul(wj, vc);
+    } else if constexpr (KIND == SK_PROBE_Z) {
+        return im_conj_mul(wj, vj) - im_conj_mul(wc, vc);
+    } else if constexpr (KIND == SK_PROBE_P1) {
+        return im_conj_mul(wc, vc);
+    } else {
+        const cpx<T> m0 = gmat<T>(G, 0), m1 = gmat<T>(G, 1), m2 = gmat<T>(G, 2), m3 = gmat<T>(G, 3);
+        const cpx<T> z0 = cfma(m0, vj, cmul(m1, vc));
+        const cpx<T> z1 = cfma(m2, vj, cmul(m3, vc));
+        return im_conj_mul(wj, z0) + im_conj_mul(wc, z1);
+    }
+}
+
+template <typename T, int W, int P, int KIND>
 __device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
                                             uint32_t gb, const TileGate &G) {
     constexpr int D = 1 << W;
-    const cpx<T> m0 = gmat<T>(G, 0), m1 = gmat<T>(G, 1), m2 = gmat<T>(G, 2), m3 = gmat<T>(G, 3);
     double acc = 0.0;
     if ((gb & G.lane) != G.lane) return acc;
 #pragma unroll
@@ -154,22 +182,36 @@ __device__ __forceinline__ double probe_pos(const cpx<T> (&v)[1 << W], const cpx
         if (j & (1 << P)) continue;
         if (!((G.amask >> j) & 1u)) continue;
         const int c = j | (1 << P);
-        const cpx<T> z0 = cfma(m0, v[j], cmul(m1, v[c]));
-        const cpx<T> z1 = cfma(m2, v[j], cmul(m3, v[c]));
-        acc += im_conj_mul(w[j], z0) + im_conj_mul(w[c], z1);
+        acc += probe_pair<T, KIND>(v[j], v[c], w[j], w[c], G);
     }
     return acc;
+}
+
+template <typename T, int W, int KIND>
+__device__ __forceinline__ double probe_kind(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
+                                             uint32_t gb, const TileGate &G) {
+    const int p = G.b0;
+    if (p == 0) return probe_pos<T, W, 0, KIND>(v, w, gb, G);
+    if constexpr (W >= 2) if (p == 1) return probe_pos<T, W, 1, KIND>(v, w, gb, G);
+    if constexpr (W >= 3) if (p == 2) return probe_pos<T, W, 2, KIND>(v, w, gb, G);
+    if constexpr (W >= 4) if (p == 3) return probe_pos<T, W, 3, KIND>(v, w, gb, G);
+    return 0.0;
+}
+
+__device__ __forceinline__ bool is_probe(int kind) {
+    return kind == SK_PARAM || (kind >= SK_PROBE_X && kind <= SK_PROBE_P1);
 }
 
 template <typename T, int W>
 __device__ __forceinline__ double probe_gate(const cpx<T> (&v)[1 << W], const cpx<T> (&w)[1 << W],
                                              uint32_t gb, const TileGate &G) {
-    const int p = G.b0;
-    if (p == 0) return probe_pos<T, W, 0>(v, w, gb, G);
-    if constexpr (W >= 2) if (p == 1) return probe_pos<T, W, 1>(v, w, gb, G);
-    if constexpr (W >= 3) if (p == 2) return probe_pos<T, W, 2>(v, w, gb, G);
-    if constexpr (W >= 4) if (p == 3) return probe_pos<T, W, 3>(v, w, gb, G);
-    return 0.0;
+    switch (G.kind) {
+    case SK_PROBE_X: return probe_kind<T, W, SK_PROBE_X>(v, w, gb, G);
+    case SK_PROBE_Y: return probe_kind<T, W, SK_PROBE_Y>(v, w, gb, G);
+    case SK_PROBE_Z: return probe_kind<T, W, SK_PROBE_Z>(v, w, gb, G);
+    case SK_PROBE_P1: return probe_kind<T, W, SK_PROBE_P1>(v, w, gb, G);
+    default: return probe_kind<T, W, SK_PARAM>(v, w, gb, G);
+    }
 }
 
 template <typename T, int W, bool TWOQ>
@@ -225,8 +267,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                 const uint32_t gb = group_bits<W>(S, act ? g : 0u);
                 const uint32_t pg = lds_phys<T>(gb);
                 const uint64_t row = base | tile_offset(sp, gb);
-                cpx<T> v[D], w[D];
-                PhaseAcc<T, W> acc_unused;
+                // psi's group in vw[0, D), lam's in vw[D, 2D): one record walk
+                // applies each gate to both, as a gate on W + 1 register
+                // positions whose top position (the vector) no gate targets
+                cpx<T> vw[2 * D];
+                cpx<T>(&v)[D] = *reinterpret_cast<cpx<T>(*)[D]>(&vw[0]);
+                cpx<T>(&w)[D] = *reinterpret_cast<cpx<T>(*)[D]>(&vw[D]);
+                PhaseAcc<T, W + 1> acc_unused;
                 acc_unused.init();
                 if (first) {
 #pragma unroll
@@ -245,16 +292,18 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                 for (int gi = 0; gi < ng; ++gi) {
                     const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
                     rp += G.size;
-                    if (G.kind == SK_PARAM) {
+                    if (is_probe(G.kind)) {
                         if ((base & G.cout) != G.cout) continue; // uniform
                         const double mine = act ? probe_gate<T, W>(v, w, gb, G) : 0.0;
                         const double c = wave_sum_d(mine);
                         if ((threadIdx.x & 63) == 0) slot_acc[threadIdx.x >> 6][G.b1] += c;
                     } else {
                         // adjoint passes carry no gathered phases (their
-                        // probes read the amplitudes between gates)
-                        sweep_gate_t<T, W, TWOQ>(v, acc_unused, gb, G, base);
-                        sweep_gate_t<T, W, TWOQ>(w, acc_unused, gb, G, base);
+                        // probes read the amplitudes between gates); the
+                        // register-index mask repeats for lam's half
+                        GateHot h = *reinterpret_cast<const GateHot *>(&G);
+                        h.amask |= h.amask << D;
+                        sweep_gate_h<T, W + 1, TWOQ>(vw, acc_unused, gb, h, G, base);
                     }
                 }
                 if (act) {

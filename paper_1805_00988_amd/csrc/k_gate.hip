@@ -39,33 +39,59 @@ struct Vec<double> {
 
 constexpr int kStreamThreads = 256;
 
+// 16-byte access, nontemporal when NT.  Launchers pick NT only when every
+// wavefront access is a run of at least 128 contiguous bytes: nontemporal
+// accesses to interleaved shorter runs (a gate on the lowest qubits) were
+// measured much slower.
+template <bool NT, typename V>
+__device__ __forceinline__ V ld16(const V *p) {
+    if constexpr (NT) return ld_nt(p);
+    else return *p;
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st16(V *p, V v) {
+    if constexpr (NT) st_nt(p, v);
+    else *p = v;
+}
+constexpr int kMinNtRunBits = 3; // 2^3 16-byte vectors = 128 bytes
+
 static inline uint64_t grid_for(uint64_t work_items, uint64_t per_block, uint64_t cap) {
     uint64_t b = (work_items + per_block - 1) / per_block;
     return std::max<uint64_t>(1, std::min<uint64_t>(b, cap));
 }
 
 // ---------------------------------------------------------------- init
-template <typename T>
+// UNROLL vectors per thread and round; a grid of up to 2^20 workgroups
+// covers a 32 GiB state in one round (measured faster than fewer
+// workgroups looping).
+template <typename T, int UNROLL>
 __global__ __launch_bounds__(kStreamThreads) void k_init_basis(typename Vec<T>::type *v,
                                                                uint64_t n_vec, uint64_t x) {
     using V = Vec<T>;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_vec; e += stride) {
-        typename V::type z;
-        for (int k = 0; k < V::amps; ++k)
-            V::put(z, k, cpx<T>{(((e << V::bits) | k) == x) ? T(1) : T(0), T(0)});
-        v[e] = z;
+    const uint64_t per_block = (uint64_t)UNROLL * kStreamThreads;
+    for (uint64_t base = (uint64_t)blockIdx.x * per_block; base < n_vec;
+         base += (uint64_t)gridDim.x * per_block) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t e = base + (uint64_t)u * kStreamThreads + threadIdx.x;
+            if (e >= n_vec) break;
+            typename V::type z;
+            for (int k = 0; k < V::amps; ++k)
+                V::put(z, k, cpx<T>{(((e << V::bits) | k) == x) ? T(1) : T(0), T(0)});
+            v[e] = z;
+        }
     }
 }
 
 hipError_t launch_init_basis(void *amps, int n, int dtype, uint64_t x, hipStream_t s) {
     const uint64_t N = 1ull << n;
-    if (dtype == SV_C64) {
-        const uint64_t nv = N / 2;
-        k_init_basis<float><<<dim3((unsigned)grid_for(nv, kStreamThreads, 65536)), dim3(kStreamThreads), 0, s>>>((float4 *)amps, nv, x);
-    } else {
-        k_init_basis<double><<<dim3((unsigned)grid_for(N, kStreamThreads, 65536)), dim3(kStreamThreads), 0, s>>>((double2 *)amps, N, x);
-    }
+    constexpr int U = 4;
+    const uint64_t nv = dtype == SV_C64 ? N / 2 : N;
+    const dim3 grid((unsigned)grid_for(nv, (uint64_t)U * kStreamThreads, 1ull << 20));
+    if (dtype == SV_C64)
+        k_init_basis<float, U><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, nv, x);
+    else
+        k_init_basis<double, U><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, nv, x);
     return hipGetLastError();
 }
 
@@ -73,7 +99,7 @@ hipError_t launch_init_basis(void *amps, int n, int dtype, uint64_t x, hipStream
 // Element-pair j -> element a (bit te clear, control bits set) and a | 2^te.
 // lane_ctrl holds control bits below the vector width (amplitude bits inside
 // one 16-byte element): only amplitudes with all of them set are updated.
-template <typename T, int UNROLL>
+template <typename T, int UNROLL, bool NT>
 __global__ __launch_bounds__(kStreamThreads) void k_gate1(typename Vec<T>::type *v, Enum e, int te,
                                                           uint64_t count, Mat2<T> g,
                                                           uint32_t lane_ctrl) {
@@ -92,8 +118,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_gate1(typename Vec<T>::type 
             ok[u] = (j < count) && ((a & e.check) == e.check);
             ia[u] = a;
             if (ok[u]) {
-                va[u] = v[a];
-                vb[u] = v[a + bstep];
+                va[u] = ld16<NT>(&v[a]);
+                vb[u] = ld16<NT>(&v[a + bstep]);
             }
         }
 #pragma unroll
@@ -107,14 +133,14 @@ __global__ __launch_bounds__(kStreamThreads) void k_gate1(typename Vec<T>::type 
                 V::put(oa, k, cfma(g.m[0], x0, cmul(g.m[1], x1)));
                 V::put(ob, k, cfma(g.m[2], x0, cmul(g.m[3], x1)));
             }
-            v[ia[u]] = oa;
-            v[ia[u] + bstep] = ob;
+            st16<NT>(&v[ia[u]], oa);
+            st16<NT>(&v[ia[u] + bstep], ob);
         }
     }
 }
 
 // complex64 gate on qubit 0: both amplitudes of a pair sit in one float4.
-template <int UNROLL>
+template <int UNROLL, bool NT>
 __global__ __launch_bounds__(kStreamThreads) void k_gate1_q0(float4 *v, Enum e, uint64_t count,
                                                              Mat2<float> g) {
     const uint64_t per_block = (uint64_t)UNROLL * kStreamThreads;
@@ -129,7 +155,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_gate1_q0(float4 *v, Enum e, 
             const uint64_t a = expand(e, j < count ? j : 0);
             ok[u] = (j < count) && ((a & e.check) == e.check);
             ia[u] = a;
-            if (ok[u]) w[u] = v[a];
+            if (ok[u]) w[u] = ld16<NT>(&v[a]);
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -137,7 +163,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_gate1_q0(float4 *v, Enum e, 
             const cpx<float> x0{w[u].x, w[u].y}, x1{w[u].z, w[u].w};
             const cpx<float> y0 = cfma(g.m[0], x0, cmul(g.m[1], x1));
             const cpx<float> y1 = cfma(g.m[2], x0, cmul(g.m[3], x1));
-            v[ia[u]] = float4{y0.re, y0.im, y1.re, y1.im};
+            st16<NT>(&v[ia[u]], float4{y0.re, y0.im, y1.re, y1.im});
         }
     }
 }
@@ -173,6 +199,12 @@ static Enum make_enum(int vbits, const int *zero_pos, int n_zero, uint64_t ctrl,
     return e;
 }
 
+// Every enumerated element index lies in a run of 2^pos[0] consecutive
+// vectors (the lowest inserted bit), and checked controls thin the runs out.
+static bool nt_ok(const Enum &e) {
+    return e.check == 0 && (e.n_pos == 0 || e.pos[0] >= kMinNtRunBits);
+}
+
 template <typename T>
 static Mat2<T> to_mat2(const double *U) {
     Mat2<T> g;
@@ -194,7 +226,11 @@ hipError_t launch_gate1(void *amps, int n, int dtype, int t, uint64_t ctrl, cons
         Enum e = make_enum(vbits, nullptr, 0, ctrl, &lane_ctrl, &np);
         const uint64_t count = n_el >> np;
         const uint64_t per = (uint64_t)kUnroll * kStreamThreads;
-        k_gate1_q0<kUnroll><<<dim3((unsigned)grid_for(count, per, kGridCap)), dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, to_mat2<float>(U));
+        const dim3 grid((unsigned)grid_for(count, per, kGridCap));
+        if (nt_ok(e))
+            k_gate1_q0<kUnroll, true><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, to_mat2<float>(U));
+        else
+            k_gate1_q0<kUnroll, false><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, to_mat2<float>(U));
         return hipGetLastError();
     }
     const int te = t - vbits;
@@ -202,17 +238,22 @@ hipError_t launch_gate1(void *amps, int n, int dtype, int t, uint64_t ctrl, cons
     const uint64_t count = n_el >> np;
     const uint64_t per = (uint64_t)kUnroll * kStreamThreads;
     const dim3 grid((unsigned)grid_for(count, per, kGridCap));
-    if (dtype == SV_C64)
-        k_gate1<float, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te, count, to_mat2<float>(U), lane_ctrl);
+    const bool nt = nt_ok(e);
+    if (dtype == SV_C64 && nt)
+        k_gate1<float, kUnroll, true><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te, count, to_mat2<float>(U), lane_ctrl);
+    else if (dtype == SV_C64)
+        k_gate1<float, kUnroll, false><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te, count, to_mat2<float>(U), lane_ctrl);
+    else if (nt)
+        k_gate1<double, kUnroll, true><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te, count, to_mat2<double>(U), lane_ctrl);
     else
-        k_gate1<double, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te, count, to_mat2<double>(U), lane_ctrl);
+        k_gate1<double, kUnroll, false><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te, count, to_mat2<double>(U), lane_ctrl);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------- streamed 2q gate
 // Quad index q = b0 + 2 b1 (bit j of q = value of targets[j]); both targets
 // at or above the vector width.
-template <typename T, int UNROLL>
+template <typename T, int UNROLL, bool NT>
 __global__ __launch_bounds__(kStreamThreads) void k_gate2(typename Vec<T>::type *v, Enum e, int te0,
                                                           int te1, uint64_t count, Mat4<T> g,
                                                           uint32_t lane_ctrl) {
@@ -231,10 +272,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_gate2(typename Vec<T>::type 
             ok[u] = (j < count) && ((a & e.check) == e.check);
             ia[u] = a;
             if (ok[u]) {
-                w[u][0] = v[a];
-                w[u][1] = v[a + s0];
-                w[u][2] = v[a + s1];
-                w[u][3] = v[a + s0 + s1];
+                w[u][0] = ld16<NT>(&v[a]);
+                w[u][1] = ld16<NT>(&v[a + s0]);
+                w[u][2] = ld16<NT>(&v[a + s1]);
+                w[u][3] = ld16<NT>(&v[a + s0 + s1]);
             }
         }
 #pragma unroll
@@ -255,10 +296,10 @@ __global__ __launch_bounds__(kStreamThreads) void k_gate2(typename Vec<T>::type 
                     V::put(o[r], k, acc);
                 }
             }
-            v[ia[u]] = o[0];
-            v[ia[u] + s0] = o[1];
-            v[ia[u] + s1] = o[2];
-            v[ia[u] + s0 + s1] = o[3];
+            st16<NT>(&v[ia[u]], o[0]);
+            st16<NT>(&v[ia[u] + s0], o[1]);
+            st16<NT>(&v[ia[u] + s1], o[2]);
+            st16<NT>(&v[ia[u] + s0 + s1], o[3]);
         }
     }
 }
@@ -283,10 +324,15 @@ hipError_t launch_gate2(void *amps, int n, int dtype, int t0, int t1, uint64_t c
     constexpr int U2 = 2;
     const uint64_t per = (uint64_t)U2 * kStreamThreads;
     const dim3 grid((unsigned)grid_for(count, per, kGridCap));
-    if (dtype == SV_C64)
-        k_gate2<float, U2><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te[0], te[1], count, to_mat4<float>(U), lane_ctrl);
+    const bool nt = nt_ok(e);
+    if (dtype == SV_C64 && nt)
+        k_gate2<float, U2, true><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te[0], te[1], count, to_mat4<float>(U), lane_ctrl);
+    else if (dtype == SV_C64)
+        k_gate2<float, U2, false><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, te[0], te[1], count, to_mat4<float>(U), lane_ctrl);
+    else if (nt)
+        k_gate2<double, U2, true><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te[0], te[1], count, to_mat4<double>(U), lane_ctrl);
     else
-        k_gate2<double, U2><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te[0], te[1], count, to_mat4<double>(U), lane_ctrl);
+        k_gate2<double, U2, false><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, te[0], te[1], count, to_mat4<double>(U), lane_ctrl);
     return hipGetLastError();
 }
 
@@ -294,7 +340,7 @@ hipError_t launch_gate2(void *amps, int n, int dtype, int t0, int t1, uint64_t c
 // Multiply every amplitude x with (x & mask) == mask by a complex factor:
 // a phase-type diagonal gate (diag(1, f), optionally controlled) only changes
 // the amplitudes whose target and control bits are all 1.
-template <typename T, int UNROLL>
+template <typename T, int UNROLL, bool NT>
 __global__ __launch_bounds__(kStreamThreads) void k_scale(typename Vec<T>::type *v, Enum e,
                                                           uint64_t count, cpx<T> f,
                                                           uint32_t lane_set) {
@@ -311,7 +357,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_scale(typename Vec<T>::type 
             const uint64_t a = expand(e, j < count ? j : 0);
             ok[u] = (j < count) && ((a & e.check) == e.check);
             ia[u] = a;
-            if (ok[u]) w[u] = v[a];
+            if (ok[u]) w[u] = ld16<NT>(&v[a]);
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -321,7 +367,7 @@ __global__ __launch_bounds__(kStreamThreads) void k_scale(typename Vec<T>::type 
                 if (((uint32_t)k & lane_set) != lane_set) continue;
                 V::put(w[u], k, cmul(f, V::get(w[u], k)));
             }
-            v[ia[u]] = w[u];
+            st16<NT>(&v[ia[u]], w[u]);
         }
     }
 }
@@ -336,10 +382,17 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
     const uint64_t count = n_el >> np;
     const uint64_t per = (uint64_t)kUnroll * kStreamThreads;
     const dim3 grid((unsigned)grid_for(count, per, kGridCap));
-    if (dtype == SV_C64)
-        k_scale<float, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, cpx<float>{(float)factor[0], (float)factor[1]}, lane_set);
+    const cpx<float> f32{(float)factor[0], (float)factor[1]};
+    const cpx<double> f64{factor[0], factor[1]};
+    const bool nt = nt_ok(e);
+    if (dtype == SV_C64 && nt)
+        k_scale<float, kUnroll, true><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, f32, lane_set);
+    else if (dtype == SV_C64)
+        k_scale<float, kUnroll, false><<<grid, dim3(kStreamThreads), 0, s>>>((float4 *)amps, e, count, f32, lane_set);
+    else if (nt)
+        k_scale<double, kUnroll, true><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, count, f64, lane_set);
     else
-        k_scale<double, kUnroll><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, count, cpx<double>{factor[0], factor[1]}, lane_set);
+        k_scale<double, kUnroll, false><<<grid, dim3(kStreamThreads), 0, s>>>((double2 *)amps, e, count, f64, lane_set);
     return hipGetLastError();
 }
 
@@ -359,6 +412,10 @@ constexpr int kTileThreads = 512;
 // batch kernel keeps 8192-amplitude complex64 tiles (whole circuits of up
 // to 13 qubits in one workgroup).
 int tile_max_qubits(int dtype) { return dtype == SV_C64 ? 12 : 12; }
+// Largest tile a tile pass accepts: the fused path's complex64 passes keep
+// 8192-amplitude tiles (64 KiB of LDS, 512 threads) when they run as plain
+// sweeps.
+int tile_launch_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
 int batch_tile_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
 
 // Register qubits per sweep: 16 complex64 or 8 complex128 amplitudes per
@@ -434,14 +491,7 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
             }
             PhaseAcc<T, W> acc;
             acc.init();
-            const char *rp = recs + S.rec_off;
-            for (int gi = 0; gi < ng; ++gi) {
-                const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
-                // advance before the gate: its inline assembly would make the
-                // compiler read the size again after it
-                rp += G.size;
-                sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
-            }
+            run_records<T, W, TWOQ>(v, acc, gb, recs + S.rec_off, ng, base);
             if (last) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) row[goff_of(j)] = v[j];
@@ -502,7 +552,7 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
                        hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
-    if (m > n || m > tile_max_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh || m < 1)
+    if (m > n || m > tile_launch_qubits(dtype) || spec.L < vbits || spec.K > kMaxTileHigh || m < 1)
         return hipErrorInvalidValue;
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);

@@ -490,12 +490,16 @@ static TileGate encode_probe(const TileSpec &sp, const std::vector<int> &qset, c
     TileGate r;
     std::memset(&r, 0, sizeof(r));
     const uint32_t cin = encode_controls(sp, g.ctrl, &r);
-    r.kind = SK_PARAM;
+    // the probes of RX, RY, RZ and U1 have their own kinds (no matrix)
+    auto is_m = [&](const double *m) { return std::memcmp(pr.M, m, sizeof(pr.M)) == 0; };
+    const double mx[8] = {0, 0, 1, 0, 1, 0, 0, 0}, my[8] = {0, 0, 0, -1, 0, 1, 0, 0};
+    const double mz[8] = {1, 0, 0, 0, 0, 0, -1, 0}, mp[8] = {0, 0, 0, 0, 0, 0, 1, 0};
+    r.kind = is_m(mx) ? SK_PROBE_X : is_m(my) ? SK_PROBE_Y : is_m(mz) ? SK_PROBE_Z : is_m(mp) ? SK_PROBE_P1 : SK_PARAM;
     const int lb = local_bit(sp, g.t[0]);
     r.b0 = (int)(std::find(qset.begin(), qset.end(), lb) - qset.begin());
     r.b1 = pr.slot;
     encode_sweep_masks(qset, cin, 1u << r.b0, 0, &r);
-    put_matrix(r, pr.M, 4, f32);
+    if (r.kind == SK_PARAM) put_matrix(r, pr.M, 4, f32);
     return r;
 }
 
@@ -647,25 +651,53 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         cur.clear();
         qset.clear();
     };
-    for (size_t i = 0; i < gs.size(); ++i) {
-        const Gate *g = gs[i];
-        if (is_diag1(*g) && !probe_of(i)) {
+    // Each sweep takes the gates, in order, whose targets fit its register
+    // set, and also looks past a gate that does not fit: a later gate may
+    // join the sweep if it shares no qubit with any gate left behind (gates
+    // on disjoint qubits commute; a probe's value is unchanged by moving a
+    // gate on other qubits across it, since that gate and its inverse cancel
+    // around the probe's Pauli).  Fewer sweeps mean fewer exchanges of the
+    // tile through LDS.
+    std::vector<char> done(gs.size(), 0);
+    size_t first = 0;
+    while (first < gs.size()) {
+        uint64_t blocked = 0; // qubits of the gates left behind by this sweep
+        for (size_t i = first; i < gs.size(); ++i) {
+            if (done[i]) continue;
+            const Gate *g = gs[i];
+            const uint64_t qm = g->qmask();
+            if (qm & blocked) {
+                blocked |= qm;
+                continue;
+            }
+            if (is_diag1(*g) && !probe_of(i)) {
+                cur.push_back(i);
+                done[i] = 1;
+                continue;
+            }
+            std::vector<int> need;
+            for (int j = 0; j < g->k; ++j) {
+                const int lb = local_bit(sp, g->t[j]);
+                if (std::find(qset.begin(), qset.end(), lb) == qset.end()) need.push_back(lb);
+            }
+            if ((int)(qset.size() + need.size()) > W) {
+                blocked |= qm;
+                continue;
+            }
+            qset.insert(qset.end(), need.begin(), need.end());
             cur.push_back(i);
-            continue;
+            done[i] = 1;
         }
-        std::vector<int> need;
-        for (int j = 0; j < g->k; ++j) {
-            const int lb = local_bit(sp, g->t[j]);
-            if (std::find(qset.begin(), qset.end(), lb) == qset.end()) need.push_back(lb);
+        // the first open gate fits an empty register set whenever W >= k;
+        // should it not, it still gets a sweep of its own (the loop ends)
+        if (cur.empty() && !done[first]) {
+            for (int j = 0; j < gs[first]->k; ++j) qset.push_back(local_bit(sp, gs[first]->t[j]));
+            cur.push_back(first);
+            done[first] = 1;
         }
-        if ((int)(qset.size() + need.size()) > W) close();
-        for (int j = 0; j < g->k; ++j) {
-            const int lb = local_bit(sp, g->t[j]);
-            if (std::find(qset.begin(), qset.end(), lb) == qset.end()) qset.push_back(lb);
-        }
-        cur.push_back(i);
+        close();
+        while (first < gs.size() && done[first]) ++first;
     }
-    close();
     pack_records(pc, f32);
     // the first and last sweeps read / write the state directly (measured
     // faster than staging the tile through LDS for every register layout,
@@ -1137,6 +1169,12 @@ static bool mfma_ok(const sv_state *h, int k, int prec) {
 // blocks (narrower blocks are padded with identity qubits), whether it runs
 // on the matrix cores, and its blocks' positions and padded matrices.
 struct FusedPass {
+    // a pass of the fused path runs either its dense blocks on the matrix
+    // cores (below) or, where the cost model prefers it, its gates as plain
+    // register sweeps on the same tile (k_tile, 'code')
+    bool plain = false;
+    PassCode code;
+    double cost = 0.0; // modelled time, ms per 2^30 amplitudes
     TileSpec sp{};
     int m = 0;
     double flops_per_amp = 0.0; // 8 * 2^k per block of k qubits (complex matvec as real flops)
@@ -1187,6 +1225,7 @@ static uint64_t tile_global_offset(const TileSpec &sp, uint32_t l) {
 }
 
 static size_t fused_pass_bytes(const sv_state *h, const FusedPass &fp) {
+    if (fp.plain) return fp.code.bytes();
     size_t b = align256(fp.blocks.size() * sizeof(DenseBlock));
     for (const auto &vs : fp.mats) b += dense_op_bytes(h, fp.k, fp.m, fp.engine, vs.size());
     return b;
@@ -1288,6 +1327,49 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
 // the tile; a diagonal gate of at most kMaxVariantQubits qubits needs none
 // of its qubits there (those outside select a variant of its block's
 // matrix per tile).
+// Cost model of one pass, in ms per 2^30 amplitudes, fitted to kernel times
+// measured on the MI355X (30-qubit complex64 fusion workload and the 32-qubit
+// complex64 headline passes; complex128 scaled by its measured per-amplitude
+// ratio).  A matrix-core pass costs its streaming floor plus a share per
+// block by width and engine; a plain pass its floor plus shares per sweep
+// (LDS exchange and barrier), per record, per gathered phase and per vector
+// ALU operation.  It only ranks the alternatives of one pass.
+static double fused_pass_cost(const sv_state *h, const FusedPass &fp) {
+    const bool c64 = h->dtype == SV_C64;
+    double t = c64 ? 3.4 : 6.5;
+    for (const DenseBlock &db : fp.blocks) {
+        const int k = db.bp.k;
+        switch (fp.engine) {
+        case SV_PREC_SPLIT_BF16: t += k <= 4 ? 0.34 : 0.65; break;
+        case SV_PREC_FP32: t += k <= 4 ? 0.77 : 1.83; break;
+        case kPrecMfma64: t += k <= 4 ? 1.5 : 3.2; break;
+        default: t += c64 ? 0.12 * (1 << k) : 0.25 * (1 << k); break; // vector ALUs
+        }
+    }
+    return t;
+}
+
+static double plain_pass_cost(const sv_state *h, const PassCode &pc) {
+    double valu = 0.0, entries = 0.0;
+    const int D = 1 << std::min(pc.m, sweep_width(h->dtype));
+    for (const TileGate &r : pc.gates) {
+        const int en = __builtin_popcount(r.amask);
+        switch (r.kind) {
+        case SK_GEN: valu += 16 + 16 * en; break;
+        case SK_REAL: case SK_RIMAG: valu += 8 + 8 * en; break;
+        case SK_SWAP: valu += 2 * en; break;
+        case SK_DIAG: case SK_DIAGR: valu += 8 + 4 * en; break;
+        case SK_2Q: valu += 64 * en; break;
+        case SK_PHASE: valu += 6 + 6 * r.b1; entries += r.b1; break;
+        case SK_FLUSH: valu += 4.0 * D * __builtin_popcount(r.amask); break;
+        default: break;
+        }
+    }
+    const double t = 1.31 + 0.58 * (double)pc.sweeps.size() + 0.057 * (double)pc.gates.size() + 0.017 * entries +
+                     4.4e-5 * valu;
+    return h->dtype == SV_C64 ? t : 2.5 * t;
+}
+
 static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::vector<Gate> &gs, int k_max,
                                                   int prec, int *n_blocks) {
     const int mmax = std::min(h->n, fused_tile_qubits(h->dtype));
@@ -1309,11 +1391,53 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
         }
         TileSpec sp{};
         tile_layout(h->n, mmax, fused_lmin(h), needed, &sp);
-        const std::vector<Block> bs = fuse_tile(sub, k_max, tile_qubits(sp));
-        std::vector<int> idx(bs.size());
-        for (size_t b = 0; b < bs.size(); ++b) idx[b] = (int)b;
-        out.push_back(build_fused_pass(h, sp, bs, idx, prec));
-        *n_blocks += (int)bs.size();
+        const uint64_t S = tile_qubits(sp);
+        // candidates: blocks of at most k_max qubits, of at most 4 (when
+        // k_max is 5), and the pass's gates as plain sweeps; the cheapest
+        // by the cost model runs
+        FusedPass best;
+        int best_blocks = 0;
+        best.cost = 1e300;
+        // fuse_tile needs every gate's tile qubits to fit one block
+        int widest = 1;
+        for (const Gate &g : sub) widest = std::max(widest, __builtin_popcountll(g.qmask() & S));
+        std::vector<int> widths{k_max};
+        if (k_max == 5 && widest <= 4) widths.push_back(4);
+        for (int kk : widths) {
+            const std::vector<Block> bs = fuse_tile(sub, kk, S);
+            std::vector<int> idx(bs.size());
+            for (size_t b = 0; b < bs.size(); ++b) idx[b] = (int)b;
+            FusedPass fp = build_fused_pass(h, sp, bs, idx, prec);
+            fp.cost = fused_pass_cost(h, fp);
+            if (fp.cost < best.cost) {
+                best = std::move(fp);
+                best_blocks = (int)bs.size();
+            }
+        }
+        const int mtile = sp.L + sp.K;
+        bool plain_ok = mtile <= tile_launch_qubits(h->dtype);
+        std::vector<Gate> local;
+        local.reserve(sub.size());
+        for (const Gate &g : sub) {
+            local.push_back(retarget_phase(g, S));
+            plain_ok = plain_ok && (tile_need(local.back()) & ~S) == 0 && !needs_tile(h, g);
+        }
+        if (plain_ok) {
+            std::vector<const Gate *> ptrs;
+            for (const Gate &g : local) ptrs.push_back(&g);
+            FusedPass fp;
+            fp.plain = true;
+            fp.sp = sp;
+            fp.m = mtile;
+            fp.code = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64);
+            fp.cost = plain_pass_cost(h, fp.code);
+            if (fp.cost < best.cost) {
+                best = std::move(fp);
+                best_blocks = 0;
+            }
+        }
+        out.push_back(std::move(best));
+        *n_blocks += best_blocks;
     }
     return out;
 }
@@ -1406,6 +1530,7 @@ static void stage_fused(sv_state *h, FusedPass &fp, size_t off) {
 }
 
 static int launch_fused(sv_state *h, const FusedPass &fp, size_t off) {
+    if (fp.plain) return launch_pass(h, fp.code, off);
     Timed tm(h, K_FUSED, 2.0 * state_bytes(h), fp.flops_per_amp * (double)(1ull << h->n));
     SV_HIP(launch_dense_pass(h->amps, h->n, h->dtype, fp.sp, fp.k,
                              reinterpret_cast<const DenseBlock *>(h->d_arena + off), (int)fp.blocks.size(),
@@ -1424,7 +1549,10 @@ static int run_fused_passes(sv_state *h, std::vector<FusedPass> &fps) {
     int rc = ensure_arena(h, total);
     if (rc) return rc;
     if ((rc = stage_wait(h))) return rc;
-    for (size_t i = 0; i < fps.size(); ++i) stage_fused(h, fps[i], offs[i]);
+    for (size_t i = 0; i < fps.size(); ++i) {
+        if (fps[i].plain) stage_pass(h, fps[i].code, offs[i]);
+        else stage_fused(h, fps[i], offs[i]);
+    }
     if ((rc = upload_arena(h, total))) return rc;
     for (size_t i = 0; i < fps.size(); ++i)
         if ((rc = launch_fused(h, fps[i], offs[i]))) return rc;
@@ -2130,6 +2258,84 @@ int sv_run_fused(sv_handle h, const sv_op *ops, int n_ops, const double *params,
     std::vector<FusedPass> fps = compile_fused_gates(h, gs, kk, prec, &nb);
     if ((rc = run_fused_passes(h, fps))) return rc;
     if (n_blocks_out) *n_blocks_out = nb;
+    return SV_OK;
+}
+
+int sv_fused_tune(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params, int k_max,
+                  int prec_mask, int reps, int *k_out, int *prec_out, double *ms_out) {
+    if (!h || !k_out || !prec_out) return fail(SV_EINVAL, "NULL argument");
+    if (k_max < 0 || k_max > 5) return fail(SV_EINVAL, "k_max must be in [0, 5]");
+    if (reps < 1) reps = 1;
+    std::vector<Gate> gs;
+    int rc = parse_ops(h, h->n, ops, n_ops, params, n_params, gs);
+    if (rc) return rc;
+    int widest = 1;
+    for (const Gate &g : gs) widest = std::max(widest, __builtin_popcountll(g.qmask()));
+    // candidates: plain tile passes (k = 0), then fused widths 4 and 5 in
+    // the allowed arithmetic (complex64: FP32 and split-BF16 matrix cores;
+    // complex128: its own precision)
+    std::vector<std::pair<int, int>> cand{{0, SV_PREC_NATIVE}};
+    const std::vector<int> precs = h->dtype == SV_C64 ? std::vector<int>{SV_PREC_FP32, SV_PREC_SPLIT_BF16}
+                                                      : std::vector<int>{SV_PREC_NATIVE};
+    for (int k = 4; k <= std::min(k_max, std::min(h->n, 5)); ++k)
+        for (int p : precs)
+            if (((prec_mask >> p) & 1) && widest <= k) cand.push_back({k, p});
+    // every candidate starts from the handle's present state, kept in a copy
+    const size_t bytes = (size_t)state_bytes(h);
+    size_t free_b = 0, total_b = 0;
+    SV_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (bytes + (64u << 20) > free_b) return fail(SV_ENOMEM, "no room for a copy of the state");
+    void *saved = nullptr;
+    SV_HIP(hipMalloc(&saved, bytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = SV_OK;
+    double best = 1e300;
+    int bk = 0, bp = SV_PREC_NATIVE;
+    auto run_one = [&](int k, int p) -> int {
+        if (k == 0) return run_gates(h, gs, SV_RUN_TILED);
+        int nb = 0;
+        std::vector<FusedPass> fps = compile_fused_gates(h, gs, k, p, &nb);
+        return run_fused_passes(h, fps);
+    };
+    hipError_t e = hipMemcpyAsync(saved, h->amps, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) rc = hip_fail(e, "sv_fused_tune");
+    for (size_t c = 0; c < cand.size() && !rc; ++c) {
+        double t_min = 1e300;
+        for (int r = 0; r <= reps && !rc; ++r) { // the first run is untimed (warm-up)
+            e = hipMemcpyAsync(h->amps, saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            if (e != hipSuccess) { rc = hip_fail(e, "sv_fused_tune"); break; }
+            if ((rc = run_one(cand[c].first, cand[c].second))) break;
+            float ms = 0.0f;
+            e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = hip_fail(e, "sv_fused_tune"); break; }
+            if (r > 0) t_min = std::min(t_min, (double)ms);
+        }
+        if (!rc && t_min < best) {
+            best = t_min;
+            bk = cand[c].first;
+            bp = cand[c].second;
+        }
+    }
+    if (!rc) {
+        e = hipMemcpyAsync(h->amps, saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "sv_fused_tune");
+    } else {
+        (void)hipMemcpyAsync(h->amps, saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+        (void)hipStreamSynchronize(h->stream);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(saved);
+    if (rc) return rc;
+    *k_out = bk;
+    *prec_out = bp;
+    if (ms_out) *ms_out = best;
     return SV_OK;
 }
 

@@ -45,6 +45,31 @@ struct Mat4 {
     cpx<T> m[16];
 };
 
+// ------------------------------------------------- nontemporal accesses
+// 16-byte loads and stores for kernels that touch every byte of the state
+// once per launch (streamed gates, reductions): marked nontemporal so they
+// do not displace reusable lines in the caches (measured 5-10 % faster for
+// the in-place update and read-only streams of a 32 GiB state).
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+typedef double f64x2_nt __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const f32x4_nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x4_nt *>(p));
+    return float4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+    const f64x2_nt v = __builtin_nontemporal_load(reinterpret_cast<const f64x2_nt *>(p));
+    return double2{v.x, v.y};
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 v) {
+    const f32x4_nt w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x4_nt *>(p));
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
+    const f64x2_nt w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<f64x2_nt *>(p));
+}
+
 // ------------------------------------------------------ index enumeration
 // Positions (ascending) at which a zero bit is inserted into an enumeration
 // index, and the bits OR-ed in afterwards.  This maps a dense counter onto
@@ -90,9 +115,16 @@ enum SweepKind : int32_t {
                   // multiplies slot b0 (sweep position p: the amplitudes with
                   // register bit p set, or W: all) in lanes whose group holds
                   // 'lane'; amask 1
-    SK_FLUSH = 10 // multiply every amplitude by its gathered factors (slot W for
-                  // all, slot p for those with register bit p) and reset the
-                  // slots in amask
+    SK_FLUSH = 10, // multiply every amplitude by its gathered factors (slot W for
+                   // all, slot p for those with register bit p) and reset the
+                   // slots in amask
+    // SK_PARAM for the probes of the rotations and the phase gate: M is
+    // Pauli X, Y, Z or the projector |1><1|, whose Im<lam|M|psi> over a
+    // pair needs two to four products instead of a 2x2 product (no matrix)
+    SK_PROBE_X = 11,
+    SK_PROBE_Y = 12,
+    SK_PROBE_Z = 13,
+    SK_PROBE_P1 = 14
 };
 // Controls inside the tile are split by where they sit in the sweep: bits
 // on tile positions outside the registers ('lane') are constant over one
@@ -170,6 +202,7 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
                        int n_sweeps, const char *dev_recs, bool two_qubit, uint32_t direct,
                        hipStream_t s);
 int tile_max_qubits(int dtype);
+int tile_launch_qubits(int dtype);
 int batch_tile_qubits(int dtype);
 int sweep_width(int dtype);
 // Dense blocks of a fused tile pass: positions of the block's qubits in the
@@ -221,7 +254,7 @@ constexpr int kMaxTerms = 64;
 hipError_t launch_expectation(const void *amps, int n, int dtype, int n_terms,
                               const uint64_t *masks, const double *coeffs, double *dev_partials,
                               int n_partials, double *dev_total, hipStream_t s);
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 8192;
 // sv_expectation on a caller's state with its partial sums in the library's
 // static device array (no allocation); the same kernels and grid as
 // launch_expectation with kReduceBlocks partials

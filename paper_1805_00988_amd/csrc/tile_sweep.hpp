@@ -302,11 +302,12 @@ constexpr uint32_t index_set(uint32_t clear) {
 // one-qubit record uses, read with one batch of scalar loads per gate.
 struct GateHot {
     int32_t kind, b0, b1;
-    uint32_t lane, amask, pad;
+    uint32_t lane, amask, pad; // pad: the record's packed size (TileGate::size)
     uint64_t cout;
     uint32_t m[16];
 };
 static_assert(offsetof(TileGate, m) == offsetof(GateHot, m), "record layout");
+static_assert(offsetof(TileGate, size) == offsetof(GateHot, pad), "record layout");
 template <typename T>
 __device__ __forceinline__ cpx<T> hmat(const GateHot &h, int i) {
     const T *m = reinterpret_cast<const T *>(h.m);
@@ -458,9 +459,8 @@ __device__ __forceinline__ void phase_flush(cpx<T> (&v)[1 << W], PhaseAcc<T, W> 
 // are rewritten, keep the compiler from holding the group in place across
 // the dispatch, so passes without them use kernels without that path.
 template <typename T, int W, bool TWOQ>
-__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
-                                             const TileGate &G, uint64_t base) {
-    const GateHot h = *reinterpret_cast<const GateHot *>(&G);
+__device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
+                                             const GateHot &h, const TileGate &G, uint64_t base) {
     const int kind = h.kind;
     const bool ok = (gb & h.lane) == h.lane;
     const uint32_t am = __builtin_amdgcn_readfirstlane((base & h.cout) == h.cout ? h.amask : 0u);
@@ -518,6 +518,28 @@ __device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
             else if (p == 2) sweep_1q<T, W, 2>(v, ok, h, am);
             else sweep_1q<T, W, 3>(v, ok, h, am);
         }
+    }
+}
+
+template <typename T, int W, bool TWOQ>
+__device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
+                                             const TileGate &G, uint64_t base) {
+    const GateHot h = *reinterpret_cast<const GateHot *>(&G);
+    sweep_gate_h<T, W, TWOQ>(v, acc, gb, h, G, base);
+}
+
+// Apply the ng packed records starting at rp to one register group.  (A
+// variant that loads record i+1's head while record i is applied needs a
+// second set of scalar registers for it and spills.)
+template <typename T, int W, bool TWOQ>
+__device__ __forceinline__ void run_records(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
+                                            const char *__restrict__ rp, int ng, uint64_t base) {
+    for (int gi = 0; gi < ng; ++gi) {
+        const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
+        // advance before the gate: its inline assembly would make the
+        // compiler read the size again after it
+        rp += G.size;
+        sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
     }
 }
 

@@ -118,8 +118,9 @@ def test_block_product_full_size_tiled(dtype, n):
 @pytest.mark.parametrize("prec,k", [(sv.SV_PREC_SPLIT_BF16, 4), (sv.SV_PREC_FP32, 4), (sv.SV_PREC_SPLIT_BF16, 5)])
 def test_block_product_full_size_fused(prec, k):
     """The fusion workload's size (30 qubits, complex64) through fused tile
-    passes; per-amplitude bound of the fused arithmetic: the FP32 2-norm bound
-    for the block count plus 2^k 2^-15 per block for split-BF16 operands."""
+    passes; per-amplitude bound of the fused arithmetic: 2^k 4 eps32 (FP32)
+    or 2^k 2^-15 (split-BF16 operands) per block, plus the plain path's bound
+    for the gates of passes run as plain sweeps."""
     n = 30
     circ, blocks = C.block_product_circuit(n, 6, 40, seed=4)
     st = sv.State(n, "c64")
@@ -129,7 +130,8 @@ def test_block_product_full_size_fused(prec, k):
     ref = block_reference(circ, blocks, idx)
     per = (2 ** k) * (2.0 ** -15 if prec == sv.SV_PREC_SPLIT_BF16 else 4 * 2.0 ** -24)
     err = np.abs(got - ref)
-    check_relative(err, ref, nb * per)
+    # passes the cost model runs as plain sweeps round like sv_run
+    check_relative(err, ref, nb * per + c64_bound(len(circ)))
     assert rel_norm(err, ref) < 1e-4
     del st
     torch.cuda.empty_cache()
