@@ -428,6 +428,9 @@ def other_workload(args):
             b.run()
         dt = timed(lambda: b.run(), args.steps, torch)
         ups = sum(c.updates() for c in circs)
+        if args.no_tune:  # profile the default configuration alone
+            print(json.dumps({"batch_ms_per_step": dt / args.steps * 1e3}), flush=True)
+            return None
         tuned = b.tune(reps=2)
         dt2 = timed(lambda: b.run(), args.steps, torch)
         z_batch = b.results()
@@ -515,6 +518,9 @@ def main():
                     choices=["plain-at-scale", "fusion", "batch", "adjoint", "qft_sweep"],
                     help="plain-at-scale (default headline line); the others time the "
                          "fusion, batched, adjoint and QFT-sweep workloads on their own")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch workload: time the default launch configuration only (no tuner, no "
+                         "per-circuit comparison)")
     ap.add_argument("--sweep-max", type=int, default=24,
                     help="largest qubit count of the QFT sweep workload")
     args = ap.parse_args()
@@ -525,7 +531,9 @@ def main():
                           "state vector is a design note, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "plain-at-scale":
-        print(json.dumps(other_workload(args)), flush=True)
+        res = other_workload(args)
+        if res is not None:
+            print(json.dumps(res), flush=True)
         return
 
     import torch

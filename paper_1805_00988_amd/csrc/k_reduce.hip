@@ -65,7 +65,11 @@ __global__ __launch_bounds__(kRedThreads) void k_probs_c64(const float4 *__restr
         for (int u = 0; u < kRedUnroll; ++u) {
             const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
             const float p0 = fmaf(w[u].x, w[u].x, w[u].y * w[u].y), p1 = fmaf(w[u].z, w[u].z, w[u].w * w[u].w);
-            if (out && e < n_vec) out[e] = float2{p0, p1};
+            if (out && e < n_vec) {
+                typedef float f32x2_nt __attribute__((ext_vector_type(2)));
+                const f32x2_nt pv = {p0, p1};
+                __builtin_nontemporal_store(pv, reinterpret_cast<f32x2_nt *>(&out[e]));
+            }
             acc += (double)w[u].x * w[u].x + (double)w[u].y * w[u].y + (double)w[u].z * w[u].z +
                    (double)w[u].w * w[u].w;
         }
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(kRedThreads) void k_probs_c128(const double2 *__res
         for (int u = 0; u < kRedUnroll; ++u) {
             const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
             const double p = fma(w[u].x, w[u].x, w[u].y * w[u].y);
-            if (out && e < n) out[e] = p;
+            if (out && e < n) __builtin_nontemporal_store(p, &out[e]);
             acc += p;
         }
     }
@@ -137,27 +141,43 @@ __device__ __forceinline__ double zsum(const Terms &t, uint64_t x) {
     return h;
 }
 
+// The sum over amplitudes of p_x h(x), h as zsum; a single term (a lone
+// Z-string, the common case) keeps its mask and coefficient in registers
+// instead of walking the term list per amplitude.
+template <typename F>
+__device__ __forceinline__ double expect_terms(const Terms &t, F &&each) {
+    if (t.n == 1) {
+        const uint64_t m = t.mask[0];
+        const double c = t.coeff[0];
+        return each([&](uint64_t x) { return (__popcll(x & m) & 1) ? -c : c; });
+    }
+    return each([&](uint64_t x) { return zsum(t, x); });
+}
+
 __global__ __launch_bounds__(kRedThreads) void k_expect_c64(const float4 *__restrict__ v,
                                                             uint64_t n_vec, Terms t,
                                                             double *partials) {
     __shared__ double sh[kRedThreads / 64];
-    double acc = 0.0;
     const uint64_t per = (uint64_t)kRedUnroll * kRedThreads;
-    for (uint64_t base = (uint64_t)blockIdx.x * per; base < n_vec; base += (uint64_t)gridDim.x * per) {
-        float4 w[kRedUnroll];
+    double acc = expect_terms(t, [&](auto &&h) {
+        double a = 0.0;
+        for (uint64_t base = (uint64_t)blockIdx.x * per; base < n_vec; base += (uint64_t)gridDim.x * per) {
+            float4 w[kRedUnroll];
 #pragma unroll
-        for (int u = 0; u < kRedUnroll; ++u) {
-            const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
-            w[u] = e < n_vec ? ld_nt(&v[e]) : float4{0.f, 0.f, 0.f, 0.f};
-        }
+            for (int u = 0; u < kRedUnroll; ++u) {
+                const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
+                w[u] = e < n_vec ? ld_nt(&v[e]) : float4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
-        for (int u = 0; u < kRedUnroll; ++u) {
-            const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
-            const double p0 = (double)w[u].x * w[u].x + (double)w[u].y * w[u].y;
-            const double p1 = (double)w[u].z * w[u].z + (double)w[u].w * w[u].w;
-            acc += p0 * zsum(t, 2 * e) + p1 * zsum(t, 2 * e + 1);
+            for (int u = 0; u < kRedUnroll; ++u) {
+                const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
+                const double p0 = (double)w[u].x * w[u].x + (double)w[u].y * w[u].y;
+                const double p1 = (double)w[u].z * w[u].z + (double)w[u].w * w[u].w;
+                a += p0 * h(2 * e) + p1 * h(2 * e + 1);
+            }
         }
-    }
+        return a;
+    });
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
@@ -166,21 +186,24 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_c128(const double2 *__re
                                                              uint64_t n, Terms t,
                                                              double *partials) {
     __shared__ double sh[kRedThreads / 64];
-    double acc = 0.0;
     const uint64_t per = (uint64_t)kRedUnroll * kRedThreads;
-    for (uint64_t base = (uint64_t)blockIdx.x * per; base < n; base += (uint64_t)gridDim.x * per) {
-        double2 w[kRedUnroll];
+    double acc = expect_terms(t, [&](auto &&h) {
+        double a = 0.0;
+        for (uint64_t base = (uint64_t)blockIdx.x * per; base < n; base += (uint64_t)gridDim.x * per) {
+            double2 w[kRedUnroll];
 #pragma unroll
-        for (int u = 0; u < kRedUnroll; ++u) {
-            const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
-            w[u] = e < n ? ld_nt(&v[e]) : double2{0.0, 0.0};
-        }
+            for (int u = 0; u < kRedUnroll; ++u) {
+                const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
+                w[u] = e < n ? ld_nt(&v[e]) : double2{0.0, 0.0};
+            }
 #pragma unroll
-        for (int u = 0; u < kRedUnroll; ++u) {
-            const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
-            acc += fma(w[u].x, w[u].x, w[u].y * w[u].y) * zsum(t, e);
+            for (int u = 0; u < kRedUnroll; ++u) {
+                const uint64_t e = base + (uint64_t)u * kRedThreads + threadIdx.x;
+                a += fma(w[u].x, w[u].x, w[u].y * w[u].y) * h(e);
+            }
         }
-    }
+        return a;
+    });
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
