@@ -460,7 +460,7 @@ def other_workload(args):
         tail = {}
         for w in sorted({c.n for c in circs}):
             one = sv.Batch([next(c for c in circs if c.n == w)], "c64", z_mask=1)
-            _lib.check(lib.sv_batch_tune(one.handle, 1, None, None, None, None))
+            _lib.check(lib.sv_batch_tune(one.handle, 1, None, None, None, None, None))
             one.run()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -293,10 +293,14 @@ int sv_adjoint_grad(sv_handle h, sv_handle lam, const sv_op *ops, int n_ops,
  * sv_batch_run launches the graph (asynchronous); sv_batch_results waits and
  * copies the n_circuits results to host memory; sv_batch_output returns
  * their device address.  sv_batch_tune times the graph for every candidate
- * tile size (LDS tile of 13, 12 or 11 qubits for complex64; 12, 11, 10 for
- * complex128), sweep width (3 or 4 register qubits) and grid (1 or 2
- * workgroups per CU), reps launches each, and keeps the fastest; the chosen
- * values and their time per launch are written to the non-NULL outputs. */
+ * fusion width (0: the gates as given; 1 or 2: each circuit's gates
+ * multiplied greedily, in circuit order, into blocks of at most 1 or 2
+ * qubits, FP64 products rounded once to the state's precision), tile size
+ * (LDS tile of 13, 12 or 11 qubits for complex64; 12, 11, 10 for
+ * complex128), sweep width (3 or 4 register qubits, at most the narrowest
+ * circuit's width) and grid (1 or 2 workgroups per CU), reps launches
+ * each, and keeps the fastest; the chosen values and their time per launch
+ * are written to the non-NULL outputs. */
 enum sv_batch_flags { SV_BATCH_KEEP_STATES = 1 };
 typedef struct sv_batch *sv_batch_handle;
 int sv_batch_create(int n_circuits, const int *widths, const int64_t *op_offsets, const sv_op *ops,
@@ -306,7 +310,13 @@ int sv_batch_run(sv_batch_handle b);
 int sv_batch_results(sv_batch_handle b, double *host_out);
 void *sv_batch_output(sv_batch_handle b);
 int sv_batch_state(sv_batch_handle b, int i, void *host_out);
-int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *grid, double *best_ms);
+int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *grid, int *fuse_w,
+                  double *best_ms);
+/* Rebuild the batch's program and graph for one configuration of the
+ * tuner's space (tile_m in the tuner's three tile sizes, sweep_w 3 or 4 and
+ * at most the narrowest circuit, grid workgroups, fuse_w 0, 1 or 2);
+ * SV_EINVAL outside it. */
+int sv_batch_config(sv_batch_handle b, int tile_m, int sweep_w, int grid, int fuse_w);
 int sv_batch_free(sv_batch_handle b);
 
 /* Per-launch timing of a handle's kernels, for measurement: with timing on,

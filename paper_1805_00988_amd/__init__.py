@@ -308,11 +308,18 @@ class Batch:
         return out
 
     def tune(self, reps: int = 2):
-        m, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        m, w, g, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         t = ctypes.c_double()
         _lib.check(_lib.load().sv_batch_tune(self.handle, int(reps), ctypes.byref(m), ctypes.byref(w),
-                                             ctypes.byref(g), ctypes.byref(t)))
-        return {"tile_qubits": m.value, "sweep_width": w.value, "grid": g.value, "ms": t.value}
+                                             ctypes.byref(g), ctypes.byref(f), ctypes.byref(t)))
+        return {"tile_qubits": m.value, "sweep_width": w.value, "grid": g.value, "fuse_width": f.value,
+                "ms": t.value}
+
+    def config(self, tile_qubits: int, sweep_width: int, grid: int, fuse_width: int = 0) -> "Batch":
+        """Rebuild the program and graph for one launch configuration."""
+        _lib.check(_lib.load().sv_batch_config(self.handle, int(tile_qubits), int(sweep_width), int(grid),
+                                               int(fuse_width)))
+        return self
 
     def close(self):
         if getattr(self, "handle", None) is not None:

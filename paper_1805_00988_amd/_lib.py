@@ -25,7 +25,7 @@ EXPORTED = ("sv_state_bytes", "sv_alloc", "sv_free", "sv_set_basis", "sv_set_str
             "sv_expectation_noalloc", "sv_marginals", "sv_collapse", "sv_measure", "sv_sample",
             "sv_run", "sv_fuse", "sv_run_fused", "sv_fused_tune", "sv_adjoint_grad", "sv_batch_create",
             "sv_batch_run", "sv_batch_results", "sv_batch_output", "sv_batch_state",
-            "sv_batch_tune", "sv_batch_free", "sv_timing", "sv_timing_read", "sv_last_error",
+            "sv_batch_tune", "sv_batch_config", "sv_batch_free", "sv_timing", "sv_timing_read", "sv_last_error",
             "sv_version")
 SV_BATCH_KEEP_STATES = 1
 
@@ -87,7 +87,8 @@ _PROTOS = {
     "sv_batch_results": (_I, [_P, _DP]),
     "sv_batch_output": (_P, [_P]),
     "sv_batch_state": (_I, [_P, _I, _P]),
-    "sv_batch_tune": (_I, [_P, _I, _IP, _IP, _IP, _DP]),
+    "sv_batch_tune": (_I, [_P, _I, _IP, _IP, _IP, _IP, _DP]),
+    "sv_batch_config": (_I, [_P, _I, _I, _I, _I]),
     "sv_batch_free": (_I, [_P]),
     "sv_timing": (_I, [_P, _I]),
     "sv_timing_read": (_I, [_P, ctypes.POINTER(sv_kernel_stat), _I, _IP]),

@@ -1621,6 +1621,61 @@ struct BatchProgram {
     size_t state_bytes = 0;
 };
 
+// Fusion width of a batch program: fw = 0 keeps the gates; fw = 1 or 2
+// multiplies, greedily in circuit order, gates into blocks of at most fw
+// qubits (targets and controls; a gate may move ahead only past gates on
+// other qubits, as in fuse()), each block becoming one 2x2 or 4x4 gate.  A
+// block of a single gate keeps that gate (its cheaper record kind), and a
+// gate wider than fw passes through on its own.
+static std::vector<Gate> fuse_for_batch(const std::vector<Gate> &gs, int fw) {
+    if (fw <= 0) return gs;
+    std::vector<Gate> out;
+    std::vector<char> done(gs.size(), 0);
+    size_t first = 0;
+    while (first < gs.size()) {
+        if (__builtin_popcountll(gs[first].qmask()) > fw) {
+            out.push_back(gs[first]);
+            done[first] = 1;
+        } else {
+            uint64_t set = 0, blocked = 0;
+            std::vector<int> members;
+            for (size_t i = first; i < gs.size(); ++i) {
+                if (done[i]) continue;
+                const uint64_t gq = gs[i].qmask();
+                if ((gq & blocked) || __builtin_popcountll(set | gq) > fw) {
+                    blocked |= gq;
+                    continue;
+                }
+                set |= gq;
+                members.push_back((int)i);
+                done[i] = 1;
+            }
+            if (members.size() == 1) {
+                out.push_back(gs[members[0]]);
+            } else {
+                Block b;
+                for (uint64_t m = set; m; m &= m - 1) b.q[b.k++] = __builtin_ctzll(m);
+                const int D = 1 << b.k;
+                b.M.assign((size_t)D * D, 0.0);
+                for (int i = 0; i < D; ++i) b.M[(size_t)i * D + i] = 1.0;
+                for (int gi : members) absorb(b, gs[gi]);
+                Gate g{};
+                g.k = b.k;
+                g.t[0] = b.q[0];
+                g.t[1] = b.k == 2 ? b.q[1] : -1;
+                g.ctrl = 0;
+                for (size_t i = 0; i < b.M.size(); ++i) {
+                    g.U[2 * i] = b.M[i].real();
+                    g.U[2 * i + 1] = b.M[i].imag();
+                }
+                out.push_back(g);
+            }
+        }
+        while (first < gs.size() && done[first]) ++first;
+    }
+    return out;
+}
+
 // Compile every circuit into tile passes for tiles of at most mmax qubits
 // and sweeps of sweep_w register qubits.
 static BatchProgram compile_batch(const std::vector<int> &widths,
@@ -1713,7 +1768,7 @@ struct sv_batch {
     sv::BatchArgs args{};
     std::vector<int64_t> state_off;
     std::vector<int> n_passes;
-    int tile_m = 0, sweep_w = 0, grid = 0;
+    int tile_m = 0, sweep_w = 0, grid = 0, fuse_w = 0;
     bool two_qubit = false; // the program holds SK_2Q records
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1733,7 +1788,7 @@ static void batch_release_program(sv_batch *b) {
 }
 
 // Build, upload and capture the batch program for (tile_m, sweep_w, grid).
-static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
+static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid, int fuse_w) {
     // the kernel is instantiated for sweeps of exactly sweep_w register
     // qubits: a circuit narrower than that would have no register groups
     const int wnarrow = *std::min_element(b->widths.begin(), b->widths.end());
@@ -1743,7 +1798,12 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
     SV_HIP(hipStreamSynchronize(b->stream));
     batch_release_program(b);
     const bool keep = (b->flags & SV_BATCH_KEEP_STATES) != 0;
-    BatchProgram bp = compile_batch(b->widths, b->circ, b->dtype, tile_m, sweep_w, keep);
+    std::vector<std::vector<Gate>> fused;
+    if (fuse_w > 0) {
+        fused.reserve(b->circ.size());
+        for (const auto &c : b->circ) fused.push_back(fuse_for_batch(c, fuse_w));
+    }
+    BatchProgram bp = compile_batch(b->widths, fuse_w > 0 ? fused : b->circ, b->dtype, tile_m, sweep_w, keep);
     const size_t o_c = 0;
     const size_t o_p = align256(o_c + bp.circuits.size() * sizeof(BatchCircuit));
     const size_t o_s = align256(o_p + bp.passes.size() * sizeof(BatchPass));
@@ -1783,6 +1843,7 @@ static int batch_prepare(sv_batch *b, int tile_m, int sweep_w, int grid) {
     b->tile_m = tile_m;
     b->sweep_w = sweep_w;
     b->grid = grid;
+    b->fuse_w = fuse_w;
     b->two_qubit = bp.two_qubit;
     // one eager launch (sets kernel attributes, checks the launch), then capture
     SV_HIP(launch_batch(a, b->dtype, sweep_w, tile_m, grid, b->two_qubit, b->stream));
@@ -2519,7 +2580,7 @@ int sv_batch_create(int n_circuits, const int *widths, const int64_t *op_offsets
         sv_batch_free(b);
         return hip_fail(e, "sv_batch_create");
     }
-    const int rc = batch_prepare(b, batch_tile_qubits(dtype), sweep_width(dtype), 2 * device_cus());
+    const int rc = batch_prepare(b, batch_tile_qubits(dtype), sweep_width(dtype), 2 * device_cus(), 0);
     if (rc) {
         const std::string msg = g_last_error;
         sv_batch_free(b);
@@ -2553,7 +2614,8 @@ int sv_batch_state(sv_batch_handle b, int i, void *host_out) {
     return SV_OK;
 }
 
-int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *grid, double *best_ms) {
+int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *grid, int *fuse_w,
+                  double *best_ms) {
     if (!b) return fail(SV_EINVAL, "NULL batch");
     if (reps < 1) reps = 1;
     const int cus = device_cus();
@@ -2562,18 +2624,19 @@ int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *g
     const int ms[3] = {mtop, mtop - 1, mtop - 2};
     const int gs[2] = {cus, 2 * cus};
     double best = 1e300;
-    int bm = mtop, bw = sweep_width(b->dtype), bg = 2 * cus;
+    int bm = mtop, bw = sweep_width(b->dtype), bg = 2 * cus, bf = 0;
     hipEvent_t e0, e1;
     SV_HIP(hipEventCreate(&e0));
     SV_HIP(hipEventCreate(&e1));
     int rc = SV_OK;
     const int wnarrow = *std::min_element(b->widths.begin(), b->widths.end());
+    for (int fw = 0; fw <= 2 && !rc; ++fw)
     for (int wi = 0; wi < 2 && !rc; ++wi)
         for (int mi = 0; mi < 3 && !rc; ++mi)
             for (int gi = 0; gi < 2 && !rc; ++gi) {
                 // sweeps wider than the narrowest circuit are not candidates
                 if (ws[wi] > wnarrow) continue;
-                if ((rc = batch_prepare(b, ms[mi], ws[wi], gs[gi]))) break;
+                if ((rc = batch_prepare(b, ms[mi], ws[wi], gs[gi], fw))) break;
                 float ms_run = 0.0f;
                 hipError_t e = hipEventRecord(e0, b->stream);
                 for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, b->stream);
@@ -2590,17 +2653,29 @@ int sv_batch_tune(sv_batch_handle b, int reps, int *tile_m, int *sweep_w, int *g
                     bm = ms[mi];
                     bw = ws[wi];
                     bg = gs[gi];
+                    bf = fw;
                 }
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if ((rc = batch_prepare(b, bm, bw, bg))) return rc;
+    if ((rc = batch_prepare(b, bm, bw, bg, bf))) return rc;
     if (tile_m) *tile_m = bm;
     if (sweep_w) *sweep_w = bw;
     if (grid) *grid = bg;
+    if (fuse_w) *fuse_w = bf;
     if (best_ms) *best_ms = best;
     return SV_OK;
+}
+
+int sv_batch_config(sv_batch_handle b, int tile_m, int sweep_w, int grid, int fuse_w) {
+    if (!b) return fail(SV_EINVAL, "NULL batch");
+    const int mtop = batch_tile_qubits(b->dtype);
+    if (tile_m < mtop - 2 || tile_m > mtop) return fail(SV_EINVAL, "tile qubits outside the tuner's range");
+    if (sweep_w != 3 && sweep_w != 4) return fail(SV_EINVAL, "sweep width must be 3 or 4");
+    if (grid < 1 || grid > 64 * device_cus()) return fail(SV_EINVAL, "grid outside [1, 64 per CU]");
+    if (fuse_w < 0 || fuse_w > 2) return fail(SV_EINVAL, "fusion width must be 0, 1 or 2");
+    return batch_prepare(b, tile_m, sweep_w, grid, fuse_w);
 }
 
 int sv_batch_free(sv_batch_handle b) {

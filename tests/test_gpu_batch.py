@@ -104,6 +104,7 @@ def test_batch_autotuner_keeps_results():
     before = b.results()
     choice = b.tune(reps=1)
     assert choice["tile_qubits"] in (11, 12, 13) and choice["sweep_width"] in (3, 4)
+    assert choice["fuse_width"] in (0, 1, 2)
     b.run()
     after = b.results()
     for i, c in enumerate(circs):
@@ -128,6 +129,31 @@ def test_batch_autotuner_complex128_narrow_circuits():
     for i, c in enumerate(circs):
         ref = z_of(O.run(c), c.n, 1)
         assert abs(z[i] - ref) <= 1e-12, (i, c.n, z[i], ref)
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("fuse_w", [1, 2])
+def test_batch_fusion_widths_match_oracle(dtype, fuse_w):
+    """Each circuit's gates multiplied into blocks of at most 1 or 2 qubits
+    (FP64 products, rounded once) before the batch program is built: final
+    states and <Z_0> against the oracle, on ladder ansatz circuits (RY, RZ,
+    CNOT ladder), random circuits with CNOTs and CZ layers, and a circuit
+    with a doubly controlled gate (wider than the blocks, kept as is)."""
+    circs = mixed_circuits(dtype, 24, seed=30 + fuse_w)
+    wide = [C.Gate("H", (q,)) for q in range(6)] + [C.Gate("X", (5,), (0, 3)), C.Gate("RY", (2,), (), 0.7),
+                                                   C.Gate("U1", (4,), (1, 2), 1.3), C.Gate("RZ", (2,), (), 0.2)]
+    circs.append(C.Circuit(6, wide, 0, None, "toffoli"))
+    b = sv.Batch(circs, dtype, z_mask=1, keep_states=True)
+    b.config(13 if dtype == "c64" else 12, 4 if dtype == "c64" else 3, 64, fuse_w)
+    b.run()
+    z = b.results()
+    for i, c in enumerate(circs):
+        ref = O.run(c)
+        got = b.state(i).astype(np.complex128)
+        tol = C128_ATOL if dtype == "c128" else c64_bound(max(1, len(c)))
+        assert np.max(np.abs(got - ref)) <= tol, (i, c.n, fuse_w)
+        assert abs(z[i] - z_of(ref, c.n, 1)) <= 2 * tol, (i, c.n)
     b.close()
 
 
