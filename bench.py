@@ -428,8 +428,14 @@ def other_workload(args):
             b.run()
         dt = timed(lambda: b.run(), args.steps, torch)
         ups = sum(c.updates() for c in circs)
-        if args.no_tune:  # profile the default configuration alone
-            print(json.dumps({"batch_ms_per_step": dt / args.steps * 1e3}), flush=True)
+        if args.no_tune:  # profile one configuration alone
+            if args.batch_config:
+                m, w, g, f = (int(x) for x in args.batch_config.split(","))
+                b.config(m, w, g, f)
+                b.run()
+                dt = timed(lambda: b.run(), args.steps, torch)
+            print(json.dumps({"batch_ms_per_step": dt / args.steps * 1e3,
+                              "config": args.batch_config or "default"}), flush=True)
             return None
         tuned = b.tune(reps=2)
         dt2 = timed(lambda: b.run(), args.steps, torch)
@@ -521,6 +527,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="batch workload: time the default launch configuration only (no tuner, no "
                          "per-circuit comparison)")
+    ap.add_argument("--batch-config", default="",
+                    help="with --no-tune: tile qubits, sweep width, grid, fusion width (e.g. 13,4,512,1)")
     ap.add_argument("--sweep-max", type=int, default=24,
                     help="largest qubit count of the QFT sweep workload")
     args = ap.parse_args()
