@@ -309,6 +309,7 @@ struct PassCode {
     uint32_t direct = 0;        // kDirectFirst / kDirectLast (launch_tile)
     std::vector<TileSweep> sweeps;
     std::vector<TileGate> gates; // records in sweep order (host form)
+    std::vector<std::vector<char>> tables; // SK_PTAB payloads (descriptors and tables)
     std::vector<char> recs;      // the same, packed for the device (pack_records)
     size_t bytes() const { return align256(sweeps.size() * sizeof(TileSweep)) + recs.size(); }
 };
@@ -334,6 +335,16 @@ static void pack_records(PassCode &pc, bool f32) {
         S.rec_off = (int32_t)pc.recs.size();
         for (int k = 0; k < S.n_gates; ++k, ++gi) {
             TileGate r = pc.gates[gi];
+            if (r.kind == SK_PTAB) { // head, then its payload (index in m[0])
+                uint64_t ti;
+                std::memcpy(&ti, r.m, 8);
+                const std::vector<char> &pl = pc.tables[ti];
+                r.size = (int32_t)(kRecordHead + pl.size());
+                const char *src = reinterpret_cast<const char *>(&r);
+                pc.recs.insert(pc.recs.end(), src, src + kRecordHead);
+                pc.recs.insert(pc.recs.end(), pl.begin(), pl.end());
+                continue;
+            }
             const size_t sz = ((size_t)kRecordHead + record_payload(r, f32) + 7) & ~(size_t)7;
             r.size = (int32_t)sz;
             const char *src = reinterpret_cast<const char *>(&r);
@@ -475,6 +486,81 @@ static TileGate encode_sweep_gate(const TileSpec &sp, const std::vector<int> &qs
     return r;
 }
 
+// Phases gathered for one (slot, per-lane mask): each entry multiplies the
+// tile's factor by its phase when the tile's global index holds all bits of
+// its condition (bits outside the tile).  Entries whose conditions lie in a
+// window of at most kPtabBits consecutive index bits are replaced by a table
+// over that window: entry x is the product of the window's phases whose
+// condition holds for index bits x (the product formed in FP64, rounded
+// once), so the device takes one table entry per window instead of testing
+// and multiplying every phase.  Entries without a condition fold into the
+// first table.  Windows cover at least two entries; the rest stay a list.
+struct PhaseEntry {
+    uint64_t cond;
+    std::complex<double> ph;
+};
+struct PhaseWindow {
+    int shift, bits;
+    std::vector<std::complex<double>> tab;
+};
+static void phase_windows(const std::vector<PhaseEntry> &ents, std::vector<PhaseWindow> *wins,
+                          std::vector<PhaseEntry> *rest) {
+    std::complex<double> k0 = 1.0;
+    bool has0 = false;
+    std::vector<PhaseEntry> cond;
+    for (const PhaseEntry &e : ents) {
+        if (e.cond == 0) {
+            k0 *= e.ph;
+            has0 = true;
+        } else {
+            cond.push_back(e);
+        }
+    }
+    std::stable_sort(cond.begin(), cond.end(), [](const PhaseEntry &a, const PhaseEntry &b) {
+        return __builtin_ctzll(a.cond) < __builtin_ctzll(b.cond);
+    });
+    std::vector<char> used(cond.size(), 0);
+    for (size_t i = 0; i < cond.size(); ++i) {
+        if (used[i]) continue;
+        const int s = __builtin_ctzll(cond[i].cond);
+        if ((cond[i].cond >> s) >= (1ull << kPtabBits)) { // wider than a window
+            rest->push_back(cond[i]);
+            used[i] = 1;
+            continue;
+        }
+        std::vector<size_t> in;
+        uint64_t span = 0;
+        for (size_t j = i; j < cond.size(); ++j)
+            if (!used[j] && (cond[j].cond >> s) < (1ull << kPtabBits)) {
+                in.push_back(j);
+                span |= cond[j].cond >> s;
+            }
+        if (in.size() < 2) {
+            rest->push_back(cond[i]);
+            used[i] = 1;
+            continue;
+        }
+        PhaseWindow w;
+        w.shift = s;
+        w.bits = 64 - __builtin_clzll(span);
+        w.tab.assign((size_t)1 << w.bits, 1.0);
+        for (size_t j : in) {
+            used[j] = 1;
+            const uint64_t c = cond[j].cond >> s;
+            for (uint64_t x = 0; x < w.tab.size(); ++x)
+                if ((x & c) == c) w.tab[x] *= cond[j].ph;
+        }
+        wins->push_back(std::move(w));
+    }
+    if (has0) {
+        if (!wins->empty()) {
+            for (auto &z : (*wins)[0].tab) z *= k0;
+        } else {
+            rest->push_back({0, k0});
+        }
+    }
+}
+
 // Group the pass's gates (in order) into sweeps of at most W register
 // qubits; diagonal one-qubit gates join the current sweep whatever their
 // target, since they act per amplitude.
@@ -574,7 +660,48 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         auto flush = [&]() {
             if (!pending) return;
             for (const auto &grp : groups) {
-                const auto &ents = grp.second;
+                std::vector<PhaseEntry> all, ents_l;
+                for (const auto &e : grp.second) all.push_back({e.first, {e.second[0], e.second[1]}});
+                std::vector<PhaseWindow> wins;
+                phase_windows(all, &wins, &ents_l);
+                // tables: kPtabWindows windows per record, their descriptors
+                // in the kPtabDesc bytes after the head, then the entry 1 (unused
+                // windows point at it) and the tables
+                auto put = [f32](std::vector<char> &pl, std::complex<double> z) {
+                    if (f32) {
+                        const float f[2] = {(float)z.real(), (float)z.imag()};
+                        pl.insert(pl.end(), reinterpret_cast<const char *>(f), reinterpret_cast<const char *>(f) + 8);
+                    } else {
+                        const double f[2] = {z.real(), z.imag()};
+                        pl.insert(pl.end(), reinterpret_cast<const char *>(f),
+                                  reinterpret_cast<const char *>(f) + 16);
+                    }
+                };
+                for (size_t w0 = 0; w0 < wins.size(); w0 += (size_t)kPtabWindows) {
+                    const size_t nw = std::min(wins.size() - w0, (size_t)kPtabWindows);
+                    std::vector<char> pl(kPtabDesc, 0);
+                    put(pl, 1.0);
+                    for (size_t w = 0; w < nw; ++w) {
+                        const PhaseWindow &pw = wins[w0 + w];
+                        const uint32_t d[4] = {(uint32_t)pw.shift, (1u << pw.bits) - 1u,
+                                               (uint32_t)(pl.size() - kPtabDesc), 0u};
+                        std::memcpy(pl.data() + 16 * w, d, 16);
+                        for (const auto &z : pw.tab) put(pl, z);
+                    }
+                    TileGate r{};
+                    r.kind = SK_PTAB;
+                    r.b0 = grp.first.first;
+                    r.b1 = (int32_t)nw;
+                    r.lane = grp.first.second;
+                    r.amask = 1;
+                    const uint64_t ti = pc.tables.size();
+                    std::memcpy(r.m, &ti, 8);
+                    pc.tables.push_back(std::move(pl));
+                    pc.gates.push_back(r);
+                    ++sw.n_gates;
+                }
+                std::vector<std::pair<uint64_t, std::array<double, 2>>> ents;
+                for (const PhaseEntry &e : ents_l) ents.push_back({e.cond, {e.ph.real(), e.ph.imag()}});
                 for (size_t e0 = 0; e0 < ents.size(); e0 += (size_t)max_entries) {
                     TileGate r{};
                     r.kind = SK_PHASE;
@@ -1361,6 +1488,7 @@ static double plain_pass_cost(const sv_state *h, const PassCode &pc) {
         case SK_DIAG: case SK_DIAGR: valu += 8 + 4 * en; break;
         case SK_2Q: valu += 64 * en; break;
         case SK_PHASE: valu += 6 + 6 * r.b1; entries += r.b1; break;
+        case SK_PTAB: valu += 6 + 6 * r.b1; entries += r.b1; break;
         case SK_FLUSH: valu += 4.0 * D * __builtin_popcount(r.amask); break;
         default: break;
         }

@@ -124,8 +124,22 @@ enum SweepKind : int32_t {
     SK_PROBE_X = 11,
     SK_PROBE_Y = 12,
     SK_PROBE_Z = 13,
-    SK_PROBE_P1 = 14
+    SK_PROBE_P1 = 14,
+    // phases gathered as SK_PHASE, taken from tables: kPtabWindows windows
+    // of consecutive global index bits, described in the kPtabDesc bytes
+    // after the head by (uint32 shift, mask, byte offset, unused); the
+    // tables follow, the first entry of that area being 1 (the table of an
+    // unused window: shift 0, mask 0, offset 0); the tile's factor is the
+    // product over the windows of the entry at offset + ((base >> shift) &
+    // mask) entries; b1 counts the windows used; slot b0, 'lane' and amask
+    // as SK_PHASE
+    SK_PTAB = 15
 };
+constexpr int kPtabBits = 6;    // widest window of a phase table
+// windows per SK_PTAB record (four would hold more scalar registers than
+// the tile kernels can spare without spilling more of them)
+constexpr int kPtabWindows = 2;
+constexpr int kPtabDesc = 16 * kPtabWindows; // descriptor bytes after the record head
 // Controls inside the tile are split by where they sit in the sweep: bits
 // on tile positions outside the registers ('lane') are constant over one
 // lane's group and tested per lane; bits on register positions only select

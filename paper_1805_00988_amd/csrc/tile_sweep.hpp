@@ -479,6 +479,20 @@ __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
             u = cmul(u, cpx<T>{on ? ph.re : T(1), on ? ph.im : T(0)});
         }
         phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
+    } else if (kind == SK_PTAB) {
+        // tile factor: one table entry per window of the tile's index bits
+        // (uniform addresses, no branch: scalar loads issued together)
+        const char *tab = reinterpret_cast<const char *>(&G) + kRecordHead + kPtabDesc;
+        cpx<T> f[kPtabWindows];
+#pragma unroll
+        for (int w = 0; w < kPtabWindows; ++w) {
+            const uint32_t x = (uint32_t)(base >> h.m[4 * w]) & h.m[4 * w + 1];
+            f[w] = *reinterpret_cast<const cpx<T> *>(tab + h.m[4 * w + 2] + (size_t)x * sizeof(cpx<T>));
+        }
+        cpx<T> u = f[0];
+#pragma unroll
+        for (int w = 1; w < kPtabWindows; ++w) u = cmul(u, f[w]);
+        phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
     } else if (kind == SK_FLUSH) {
         phase_flush<T, W>(v, acc, am);
     } else if (kind == SK_DIAG) {

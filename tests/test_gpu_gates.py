@@ -242,6 +242,51 @@ def test_diagonal_gates_outside_tile(dtype, n):
     assert_state_close(got, ref, dtype, len(gates))
 
 
+def phase_table_circuit(n, seed, layers=6):
+    """Dense gates on qubits 0-5 between long runs of phase gates whose
+    targets sit on low qubits and whose controls lie on high qubits: pairs of
+    nearby high controls (gathered into tables over windows of index bits),
+    controls far apart (left as single conditions), no control (constant
+    factors), and phase gates on high targets alone."""
+    rng = np.random.default_rng(seed)
+    hi = list(range(n // 2, n))
+    gates = [C.Gate("H", (q,)) for q in range(n)]
+    for _ in range(layers):
+        for q in range(6):
+            gates.append(C.Gate(["H", "RX", "RY"][int(rng.integers(0, 3))], (q,), (), float(rng.uniform(0, 6.28))))
+        for _ in range(40):
+            t = int(rng.integers(0, 2))
+            kind = int(rng.integers(0, 5))
+            th = float(rng.uniform(0, 6.28))
+            if kind == 0:
+                c = int(rng.choice(hi))
+                gates.append(C.Gate("U1", (t,), (c,), th))
+            elif kind == 1:
+                c0 = int(rng.choice(hi[:-3]))
+                c1 = c0 + 1 + int(rng.integers(0, 3))
+                gates.append(C.Gate("U1", (t,), (c0, c1), th))
+            elif kind == 2:
+                gates.append(C.Gate("U1", (t,), (hi[0], hi[-1]), th))
+            elif kind == 3:
+                gates.append(C.Gate(["S", "T", "Z"][int(rng.integers(0, 3))], (t,)))
+            else:
+                gates.append(C.Gate("U1", (int(rng.choice(hi)),), (), th))
+    gates += [C.Gate("H", (q,)) for q in range(n)]
+    return gates
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [14, 19, 22])
+def test_phase_tables_outside_tile(dtype, n):
+    """Gathered phases conditioned on qubits outside the tile: the factor per
+    tile comes from tables over windows of index bits (products formed once
+    on the host) and from single conditions; against the oracle's gate by
+    gate application."""
+    gates = phase_table_circuit(n, 300 + n)
+    got, ref = run_both(n, dtype, gates, seed=12, mode=sv.SV_RUN_TILED)
+    assert_state_close(got, ref, dtype, len(gates))
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("mode", ["per_gate", "tiled"])
 def test_config0_random_circuit(dtype, mode):
