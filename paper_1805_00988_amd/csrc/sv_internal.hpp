@@ -102,7 +102,7 @@ enum SweepKind : int32_t {
     SK_GEN = 1,   // general 2x2 on sweep position b0
     SK_REAL = 2,  // real 2x2 (m[0], m[2], m[4], m[6] hold the entries)
     SK_DIAG = 3,  // diag(d0, d1) on tile bit b0 outside the registers; m: d0, d1
-    SK_SWAP = 4,  // X: exchange the pair (never with per-lane controls)
+    SK_SWAP = 4,  // X: exchange the pair (per-lane controls: complex64 only)
     SK_2Q = 5,    // 4x4 on sweep positions b0 < b1 (bit 0 of the matrix index <-> b0)
     SK_PARAM = 6, // adjoint sweep: add Im<lam|M|psi> for M (entries 0-3) on position b0
                   // to slot b1; the undo of the gate follows as its own record

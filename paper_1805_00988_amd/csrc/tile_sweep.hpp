@@ -253,6 +253,19 @@ __device__ __forceinline__ void rswap(cpx<double> &a, cpx<double> &b, uint32_t a
                 "v_mov_b64 %3, %5",
                 SV_OUTS("+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im), "=&v"(t0), "=&v"(t1)));
 }
+// The same exchange in the lanes of 'lm' only (per-lane controls), complex64:
+// two selects and a copy per component.
+template <int J, bool TEST>
+__device__ __forceinline__ void rswap_lanes(cpx<float> &a, cpx<float> &b, uint64_t lm, uint32_t am) {
+    float t0, t1;
+    SV_ASM("v_cndmask_b32 %4, %0, %2, %6\n\t"
+           "v_cndmask_b32 %5, %1, %3, %6\n\t"
+           "v_cndmask_b32 %2, %2, %0, %6\n\t"
+           "v_cndmask_b32 %3, %3, %1, %6\n\t"
+           "v_mov_b32 %0, %4\n\t"
+           "v_mov_b32 %1, %5",
+           SV_OUTS("+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im), "=&v"(t0), "=&v"(t1)), SV_INS("s"(lm)));
+}
 // x <- 1, in place
 __device__ __forceinline__ void rone(cpx<float> &x) {
     asm volatile("v_mov_b32 %0, 1.0\n\tv_mov_b32 %1, 0" : "+v"(x.re), "+v"(x.im));
@@ -339,8 +352,16 @@ __device__ __forceinline__ void sweep_1q(cpx<T> (&v)[1 << W], bool ok, const Gat
         const cpx<T> m1 = hmat<T>(h, 1), m2 = hmat<T>(h, 2);
         const T w[4] = {ok ? hre<T>(h, 0) : T(1), ok ? m1.im : T(0), ok ? m2.im : T(0), ok ? hre<T>(h, 3) : T(1)};
         over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rrimag<j, t>(v[j], v[j | (1 << P)], w, am); });
-    } else if (kind == SK_SWAP) { // never carries per-lane controls
-        over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rswap<j, t>(v[j], v[j | (1 << P)], am); });
+    } else if (kind == SK_SWAP) {
+        if (h.lane == 0) {
+            over_mask<PAIRS, D>(am, [&](auto jc, auto tc) { SV_J; rswap<j, t>(v[j], v[j | (1 << P)], am); });
+        } else if constexpr (std::is_same<T, float>::value) { // per-lane controls
+            const uint64_t lm = __builtin_amdgcn_ballot_w64(ok);
+            over_mask<PAIRS, D>(am, [&](auto jc, auto tc) {
+                SV_J;
+                rswap_lanes<j, t>(v[j], v[j | (1 << P)], lm, am);
+            });
+        }
     } else { // SK_DIAGR: amplitude j takes d1 if its bit P is set, else d0
         const cpx<T> one{T(1), T(0)};
         const cpx<T> d0 = ok ? hmat<T>(h, 0) : one, d1 = ok ? hmat<T>(h, 1) : one;
