@@ -1501,7 +1501,7 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
         for (int j = 0; j < bs[b].k; ++j) tm[b] |= 1ull << bs[b].q[j];
     }
     std::vector<FusedPass> out;
-    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h))) {
+    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h), true)) {
         uint64_t needed = 0;
         for (int bi : p.gates) needed |= tm[bi];
         TileSpec sp{};
@@ -1574,7 +1574,7 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
     }
     std::vector<FusedPass> out;
     *n_blocks = 0;
-    for (const Pass &p : schedule_masks(tm, qm, mmax, fused_lmin(h))) {
+    for (const Pass &p : schedule_masks(tm, qm, mmax, fused_lmin(h), true)) {
         uint64_t needed = 0;
         std::vector<Gate> sub;
         sub.reserve(p.gates.size());
