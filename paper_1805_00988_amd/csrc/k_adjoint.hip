@@ -223,8 +223,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
     constexpr int D = 1 << W;
     extern __shared__ char lds_raw[];
     const uint32_t tsize = 1u << m;
-    cpx<T> *lp = reinterpret_cast<cpx<T> *>(lds_raw);
-    cpx<T> *ll = lp + tsize;
+    // one LDS tile, used by psi and then by lam at each exchange (half the
+    // LDS of a tile per vector: more workgroups per CU)
+    cpx<T> *lt = reinterpret_cast<cpx<T> *>(lds_raw);
     // one row of slot sums per wave, written only by that wave's lane 0 (no
     // atomics): the workgroup's sums are then formed in a fixed order and the
     // gradient is the same bit for bit on every run
@@ -232,23 +233,34 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
     __shared__ double slot_acc[kWaves][kMaxAdjSlots];
     for (int i = threadIdx.x; i < kWaves * kMaxAdjSlots; i += blockDim.x) (&slot_acc[0][0])[i] = 0.0;
     __syncthreads();
+    // one register group per thread (at most blockDim groups, checked at
+    // launch); a thread past the last group holds zeros, adds 0 to the
+    // probes' wave sums and takes part in every barrier
     const uint32_t n_groups = tsize >> W;
+    const uint32_t g = threadIdx.x;
+    const bool act = g < n_groups;
     cpx<T> *ps = reinterpret_cast<cpx<T> *>(psi);
     cpx<T> *ls = reinterpret_cast<cpx<T> *>(lam);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint64_t base = tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        // the first sweep reads both vectors' register groups straight from
-        // HBM and the last writes them straight back; only the sweeps in
-        // between exchange the tiles through LDS (each sweep ends with a
-        // barrier, which also orders this tile's last LDS reads before the
-        // next tile's first LDS writes)
+        // psi's group in vw[0, D), lam's in vw[D, 2D): one record walk
+        // applies each gate to both, as a gate on W + 1 register positions
+        // whose top position (the vector) no gate targets.  The first sweep
+        // reads both groups straight from HBM and the last writes them
+        // straight back; between sweeps the groups move to the next sweep's
+        // register layout through the LDS tile, psi first, then lam.
+        cpx<T> vw[2 * D];
+        cpx<T>(&v)[D] = *reinterpret_cast<cpx<T>(*)[D]>(&vw[0]);
+        cpx<T>(&w)[D] = *reinterpret_cast<cpx<T>(*)[D]>(&vw[D]);
+        PhaseAcc<T, W + 1> acc_unused;
+        acc_unused.init();
         for (int si = 0; si < n_sweeps; ++si) {
             const TileSweep &S = sweeps[si];
             const int ng = S.n_gates;
             const bool first = si == 0, last = si == n_sweeps - 1;
-            uint32_t PF[D];
-            register_offsets<T, W>(S, PF);
+            const uint32_t gb = group_bits<W>(S, act ? g : 0u);
+            const uint64_t row = base | tile_offset(sp, gb);
             uint64_t gbit[W];
 #pragma unroll
             for (int b = 0; b < W; ++b) gbit[b] = tile_offset(sp, 1u << S.qpos[b]);
@@ -259,70 +271,69 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_tile(typename AV<T>::ty
                     if ((j >> b) & 1) o |= gbit[b];
                 return o;
             };
-            // every lane runs the same number of iterations (the probe's wave
-            // reduction needs all 64 lanes); lanes past the last group add 0
-            for (uint32_t g0 = 0; g0 < n_groups; g0 += blockDim.x) {
-                const uint32_t g = g0 + threadIdx.x;
-                const bool act = g < n_groups;
-                const uint32_t gb = group_bits<W>(S, act ? g : 0u);
-                const uint32_t pg = lds_phys<T>(gb);
-                const uint64_t row = base | tile_offset(sp, gb);
-                // psi's group in vw[0, D), lam's in vw[D, 2D): one record walk
-                // applies each gate to both, as a gate on W + 1 register
-                // positions whose top position (the vector) no gate targets
-                cpx<T> vw[2 * D];
-                cpx<T>(&v)[D] = *reinterpret_cast<cpx<T>(*)[D]>(&vw[0]);
-                cpx<T>(&w)[D] = *reinterpret_cast<cpx<T>(*)[D]>(&vw[D]);
-                PhaseAcc<T, W + 1> acc_unused;
-                acc_unused.init();
-                if (first) {
+            if (first) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        v[j] = act ? ps[row | goff_of(j)] : cpx<T>{T(0), T(0)};
-                        w[j] = act ? ls[row | goff_of(j)] : cpx<T>{T(0), T(0)};
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        v[j] = lp[pg ^ PF[j]];
-                        w[j] = ll[pg ^ PF[j]];
-                    }
-                }
-                const char *rp = recs + S.rec_off;
-                for (int gi = 0; gi < ng; ++gi) {
-                    const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
-                    rp += G.size;
-                    if (is_probe(G.kind)) {
-                        if ((base & G.cout) != G.cout) continue; // uniform
-                        const double mine = act ? probe_gate<T, W>(v, w, gb, G) : 0.0;
-                        const double c = wave_sum_d(mine);
-                        if ((threadIdx.x & 63) == 0) slot_acc[threadIdx.x >> 6][G.b1] += c;
-                    } else {
-                        // adjoint passes carry no gathered phases (their
-                        // probes read the amplitudes between gates); the
-                        // register-index mask repeats for lam's half
-                        GateHot h = *reinterpret_cast<const GateHot *>(&G);
-                        h.amask |= h.amask << D;
-                        sweep_gate_h<T, W + 1, TWOQ>(vw, acc_unused, gb, h, G, base);
-                    }
-                }
-                if (act) {
-                    if (last) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) {
-                            ps[row | goff_of(j)] = v[j];
-                            ls[row | goff_of(j)] = w[j];
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) {
-                            lp[pg ^ PF[j]] = v[j];
-                            ll[pg ^ PF[j]] = w[j];
-                        }
-                    }
+                for (int j = 0; j < D; ++j) {
+                    v[j] = act ? ps[row | goff_of(j)] : cpx<T>{T(0), T(0)};
+                    w[j] = act ? ls[row | goff_of(j)] : cpx<T>{T(0), T(0)};
                 }
             }
-            __syncthreads();
+            const char *rp = recs + S.rec_off;
+            for (int gi = 0; gi < ng; ++gi) {
+                const TileGate &G = *reinterpret_cast<const TileGate *>(rp);
+                rp += G.size;
+                if (is_probe(G.kind)) {
+                    if ((base & G.cout) != G.cout) continue; // uniform
+                    const double mine = act ? probe_gate<T, W>(v, w, gb, G) : 0.0;
+                    const double c = wave_sum_d(mine);
+                    if ((threadIdx.x & 63) == 0) slot_acc[threadIdx.x >> 6][G.b1] += c;
+                } else {
+                    // adjoint passes carry no gathered phases (their probes
+                    // read the amplitudes between gates); the register-index
+                    // mask repeats for lam's half
+                    GateHot h = *reinterpret_cast<const GateHot *>(&G);
+                    h.amask |= h.amask << D;
+                    sweep_gate_h<T, W + 1, TWOQ, false>(vw, acc_unused, gb, h, G, base);
+                }
+            }
+            if (last) {
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        ps[row | goff_of(j)] = v[j];
+                        ls[row | goff_of(j)] = w[j];
+                    }
+                }
+            } else {
+                const TileSweep &N = sweeps[si + 1];
+                uint32_t PF[D], PN[D];
+                register_offsets<T, W>(S, PF);
+                register_offsets<T, W>(N, PN);
+                const uint32_t pg = lds_phys<T>(gb);
+                const uint32_t pn = lds_phys<T>(group_bits<W>(N, act ? g : 0u));
+                // each barrier orders one vector's writes before its reads,
+                // and its reads before the next writes to the tile
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) lt[pg ^ PF[j]] = v[j];
+                }
+                __syncthreads();
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) v[j] = lt[pn ^ PN[j]];
+                }
+                __syncthreads();
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) lt[pg ^ PF[j]] = w[j];
+                }
+                __syncthreads();
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) w[j] = lt[pn ^ PN[j]];
+                }
+                __syncthreads();
+            }
         }
     }
     __syncthreads();
@@ -343,8 +354,9 @@ hipError_t launch_adjoint_tile(void *psi, void *lam, int n, int dtype, const Til
         return hipErrorInvalidValue;
     const uint64_t n_tiles = 1ull << (n - m);
     if ((uint64_t)n_blocks > n_tiles) return hipErrorInvalidValue; // every workgroup owns a tile
-    const size_t lds = 2 * (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
+    const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     const int W = std::min(m, sweep_width(dtype));
+    if (((1u << m) >> W) > (unsigned)kAdjThreads) return hipErrorInvalidValue; // one group per thread
 #define SV_ADJ_CASE(TT, VT, WW)                                                                    \
     if (W == WW) {                                                                                 \
         if (two_qubit) {                                                                           \

@@ -479,13 +479,15 @@ __device__ __forceinline__ void phase_flush(cpx<T> (&v)[1 << W], PhaseAcc<T, W> 
 // instances: their partial sums, which read the old amplitudes while others
 // are rewritten, keep the compiler from holding the group in place across
 // the dispatch, so passes without them use kernels without that path.
-template <typename T, int W, bool TWOQ>
+// PHASES = false compiles the gathered-phase kinds out, for streams that
+// carry none (the adjoint's reverse passes).
+template <typename T, int W, bool TWOQ, bool PHASES = true>
 __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
                                              const GateHot &h, const TileGate &G, uint64_t base) {
     const int kind = h.kind;
     const bool ok = (gb & h.lane) == h.lane;
     const uint32_t am = __builtin_amdgcn_readfirstlane((base & h.cout) == h.cout ? h.amask : 0u);
-    if (kind == SK_PHASE) {
+    if (PHASES && kind == SK_PHASE) {
         // tile factor: product of the entries' phases whose condition holds
         const char *e = reinterpret_cast<const char *>(&G) + kRecordHead;
         cpx<T> u{T(1), T(0)};
@@ -500,7 +502,7 @@ __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
             u = cmul(u, cpx<T>{on ? ph.re : T(1), on ? ph.im : T(0)});
         }
         phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
-    } else if (kind == SK_PTAB) {
+    } else if (PHASES && kind == SK_PTAB) {
         // tile factor: one table entry per window of the tile's index bits
         // (uniform addresses, no branch: scalar loads issued together)
         const char *tab = reinterpret_cast<const char *>(&G) + kRecordHead + kPtabDesc;
@@ -514,7 +516,7 @@ __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
 #pragma unroll
         for (int w = 1; w < kPtabWindows; ++w) u = cmul(u, f[w]);
         phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
-    } else if (kind == SK_FLUSH) {
+    } else if (PHASES && kind == SK_FLUSH) {
         phase_flush<T, W>(v, acc, am);
     } else if (kind == SK_DIAG) {
         sweep_diag_lane<T, W>(v, gb, ok, h, am);
