@@ -321,7 +321,7 @@ static size_t record_payload(const TileGate &r, bool f32) {
     case SK_2Q: return 16 * c;
     case SK_GEN: case SK_REAL: case SK_RIMAG: case SK_PARAM: return 4 * c;
     case SK_DIAG: case SK_DIAGR: return 2 * c;
-    case SK_PHASE: return (size_t)r.b1 * (8 + c); // b1 entries of (condition, phase)
+    case SK_PHASE: case SK_LPH: return (size_t)r.b1 * (8 + c); // b1 entries of (condition, phase)
     default: return 0; // SK_SWAP, SK_FLUSH
     }
 }
@@ -660,7 +660,61 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
         const int max_entries = (int)(sizeof(TileGate::m) / entry_bytes);
         auto flush = [&]() {
             if (!pending) return;
-            for (const auto &grp : groups) {
+            // groups conditioned on one lane bit and nothing outside the
+            // tile: one SK_LPH record per slot lists (bit, phase) for all of
+            // them, so the lanes walk one record instead of one per bit
+            // (complex128 only: in the complex64 kernel the extra record kind
+            // slowed the other passes more than it saved)
+            std::vector<std::vector<std::pair<uint32_t, std::complex<double>>>> lph(W + 1);
+            std::vector<char> in_lph(groups.size(), 0);
+            for (size_t gi = 0; gi < groups.size() && !f32; ++gi) {
+                const auto &grp = groups[gi];
+                const uint32_t lm = grp.first.second;
+                if (__builtin_popcount(lm) != 1) continue;
+                bool inside = true;
+                std::complex<double> ph = 1.0;
+                for (const auto &e : grp.second) {
+                    inside = inside && e.first == 0;
+                    ph *= std::complex<double>(e.second[0], e.second[1]);
+                }
+                if (!inside) continue;
+                lph[grp.first.first].push_back({lm, ph});
+                in_lph[gi] = 1;
+            }
+            for (int slot_i = 0; slot_i <= W; ++slot_i) {
+                const auto &ents = lph[slot_i];
+                if (ents.size() < 2) { // a single bit stays an SK_PHASE record
+                    for (size_t gi = 0; gi < groups.size(); ++gi)
+                        if (in_lph[gi] && groups[gi].first.first == slot_i) in_lph[gi] = 0;
+                    continue;
+                }
+                for (size_t e0 = 0; e0 < ents.size(); e0 += (size_t)max_entries) {
+                    TileGate r{};
+                    r.kind = SK_LPH;
+                    r.b0 = slot_i;
+                    r.amask = 1;
+                    const size_t ne = std::min(ents.size() - e0, (size_t)max_entries);
+                    r.b1 = (int32_t)ne;
+                    char *dst = reinterpret_cast<char *>(r.m);
+                    for (size_t e = 0; e < ne; ++e, dst += entry_bytes) {
+                        const uint64_t lm = ents[e0 + e].first;
+                        std::memcpy(dst, &lm, 8);
+                        const std::complex<double> z = ents[e0 + e].second;
+                        if (f32) {
+                            const float f[2] = {(float)z.real(), (float)z.imag()};
+                            std::memcpy(dst + 8, f, 8);
+                        } else {
+                            const double f[2] = {z.real(), z.imag()};
+                            std::memcpy(dst + 8, f, 16);
+                        }
+                    }
+                    pc.gates.push_back(r);
+                    ++sw.n_gates;
+                }
+            }
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                if (in_lph[gi]) continue;
+                const auto &grp = groups[gi];
                 std::vector<PhaseEntry> all, ents_l;
                 for (const auto &e : grp.second) all.push_back({e.first, {e.second[0], e.second[1]}});
                 std::vector<PhaseWindow> wins;
@@ -1554,6 +1608,7 @@ static double plain_pass_cost(const sv_state *h, const PassCode &pc) {
         case SK_2Q: valu += 64 * en; break;
         case SK_PHASE: valu += 6 + 6 * r.b1; entries += r.b1; break;
         case SK_PTAB: valu += 6 + 6 * r.b1; entries += r.b1; break;
+        case SK_LPH: valu += 6 + 8 * r.b1; entries += r.b1; break;
         case SK_FLUSH: valu += 4.0 * D * __builtin_popcount(r.amask); break;
         default: break;
         }

@@ -133,7 +133,12 @@ enum SweepKind : int32_t {
     // product over the windows of the entry at offset + ((base >> shift) &
     // mask) entries; b1 counts the windows used; slot b0, 'lane' and amask
     // as SK_PHASE
-    SK_PTAB = 15
+    SK_PTAB = 15,
+    // phases on lane bits (complex128 streams only): b1 entries of (uint64
+    // tile-bit mask of one bit, complex phase) laid out as SK_PHASE's; a
+    // lane's factor is the product of the phases whose bit its group holds;
+    // slot b0, amask 1
+    SK_LPH = 16
 };
 constexpr int kPtabBits = 6;    // widest window of a phase table
 // windows per SK_PTAB record (four would hold more scalar registers than

@@ -516,6 +516,19 @@ __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
 #pragma unroll
         for (int w = 1; w < kPtabWindows; ++w) u = cmul(u, f[w]);
         phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
+    } else if (PHASES && std::is_same<T, double>::value && kind == SK_LPH) {
+        // per-lane factor: the phases of the lane bits its group holds
+        const char *e = reinterpret_cast<const char *>(&G) + kRecordHead;
+        cpx<T> u{T(1), T(0)};
+#pragma unroll 2
+        for (int i = 0; i < h.b1; ++i) {
+            const char *ei = e + (size_t)i * (8 + sizeof(cpx<T>));
+            const uint32_t bm = *reinterpret_cast<const uint32_t *>(ei);
+            const cpx<T> ph = *reinterpret_cast<const cpx<T> *>(ei + 8);
+            const bool on = (gb & bm) != 0u;
+            u = cmul(u, cpx<T>{on ? ph.re : T(1), on ? ph.im : T(0)});
+        }
+        phase_gather<T, W>(acc, h.b0, u);
     } else if (PHASES && kind == SK_FLUSH) {
         phase_flush<T, W>(v, acc, am);
     } else if (kind == SK_DIAG) {
