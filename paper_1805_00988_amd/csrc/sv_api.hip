@@ -940,14 +940,80 @@ static int pass_gates(const std::vector<uint64_t> &tm, const std::vector<uint64_
     return cnt;
 }
 
+// Greedy tile set: the qubits beyond the low block are taken in the order
+// the gates first need them, while they fit.
+static uint64_t greedy_tile_set(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
+                                const std::vector<char> &done, size_t first, uint64_t low, int kmax) {
+    uint64_t S = low, blocked = 0;
+    int used = 0;
+    for (size_t i = first; i < tm.size(); ++i) {
+        if (done[i]) continue;
+        if (qm[i] & blocked) {
+            blocked |= qm[i];
+            continue;
+        }
+        const uint64_t need = tm[i] & ~S;
+        const int nn = __builtin_popcountll(need);
+        if (used + nn <= kmax) {
+            S |= need;
+            used += nn;
+        } else {
+            blocked |= qm[i];
+        }
+    }
+    return S;
+}
+
+// Lookahead tile set: the qubits beyond the low block are added one at a
+// time, among those needed by the first gates that do not fit yet (at most
+// 12 candidates), each time the one that lets the pass take the most gates;
+// the first addition takes the candidate of rank 'rank' instead of the best.
+// *count receives the gates the pass takes.
+static uint64_t lookahead_tile_set(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
+                                   const std::vector<char> &done, size_t first, uint64_t low, int kmax, int rank,
+                                   int *count) {
+    uint64_t S = low;
+    int c = pass_gates(tm, qm, done, first, S, nullptr);
+    std::vector<std::pair<int, uint64_t>> sc;
+    for (int used = 0; used < kmax; ++used) {
+        uint64_t cand = 0, blocked = 0;
+        for (size_t i = first; i < tm.size() && __builtin_popcountll(cand) < 12; ++i) {
+            if (done[i]) continue;
+            if (qm[i] & blocked) {
+                blocked |= qm[i];
+                continue;
+            }
+            if (tm[i] & ~S) {
+                cand |= tm[i] & ~S;
+                blocked |= qm[i];
+            }
+        }
+        sc.clear();
+        for (uint64_t cc = cand; cc; cc &= cc - 1) {
+            const uint64_t q = cc & (~cc + 1);
+            sc.push_back({pass_gates(tm, qm, done, first, S | q, nullptr), q});
+        }
+        std::sort(sc.begin(), sc.end(), [](const std::pair<int, uint64_t> &x, const std::pair<int, uint64_t> &y) {
+            return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
+        const size_t pick = used == 0 ? (size_t)rank : 0;
+        if (sc.size() <= pick || sc[pick].first <= c) break;
+        S |= sc[pick].second;
+        c = sc[pick].first;
+    }
+    *count = c;
+    return S;
+}
+
 // Commutation-aware pass scheduler.  Every pass holds the low lmin qubits
 // and up to mmax - lmin others.  Greedy: the others are taken in the order
-// the gates first need them.  With lookahead, they are chosen one at a time
-// among the qubits needed by the first gates that do not fit yet (at most
-// 12 candidates), each time the one that lets the pass take the most gates;
-// the pass keeps whichever of the two choices takes more gates.  (On the
-// random circuits of the benchmark: 48 -> 42 passes at 32 qubits, 36 -> 32
-// at 30 qubits.)
+// the gates first need them.  With lookahead, the pass's tile set is chosen
+// among the greedy set and kLookRanks lookahead sets (the best first
+// addition and the next best ones), by the gates this pass and the next one
+// would take together (the next pass chosen by the better of the greedy
+// and the plain lookahead set).  On the random circuits of the benchmark:
+// 48 -> 33 passes at 32 qubits, 36 -> 28 at 30 qubits.
+constexpr int kLookRanks = 9;
 static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
                                         int mmax, int lmin, bool lookahead = false) {
     std::vector<Pass> passes;
@@ -955,68 +1021,46 @@ static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const s
     size_t first = 0;
     const uint64_t low = lmin >= 64 ? ~0ull : ((1ull << lmin) - 1ull);
     const int kmax = std::max(0, mmax - lmin);
+    auto next_first = [&](const std::vector<char> &d, size_t f) {
+        while (f < tm.size() && d[f]) ++f;
+        return f;
+    };
     while (first < tm.size()) {
-        // greedy choice
-        uint64_t Sg = low;
-        {
-            uint64_t blocked = 0;
-            int used = 0;
-            for (size_t i = first; i < tm.size(); ++i) {
-                if (done[i]) continue;
-                if (qm[i] & blocked) {
-                    blocked |= qm[i];
-                    continue;
-                }
-                const uint64_t need = tm[i] & ~Sg;
-                const int nn = __builtin_popcountll(need);
-                if (used + nn <= kmax) {
-                    Sg |= need;
-                    used += nn;
-                } else {
-                    blocked |= qm[i];
-                }
-            }
-        }
-        uint64_t S = Sg;
+        uint64_t S = greedy_tile_set(tm, qm, done, first, low, kmax);
         if (lookahead) {
-            const int cg = pass_gates(tm, qm, done, first, Sg, nullptr);
-            uint64_t Sl = low;
-            int cl = pass_gates(tm, qm, done, first, Sl, nullptr);
-            for (int used = 0; used < kmax; ++used) {
-                uint64_t cand = 0, blocked = 0;
-                for (size_t i = first; i < tm.size() && __builtin_popcountll(cand) < 12; ++i) {
-                    if (done[i]) continue;
-                    if (qm[i] & blocked) {
-                        blocked |= qm[i];
-                        continue;
-                    }
-                    if (tm[i] & ~Sl) {
-                        cand |= tm[i] & ~Sl;
-                        blocked |= qm[i];
-                    }
-                }
-                int best = cl;
-                uint64_t bq = 0;
-                for (uint64_t c = cand; c; c &= c - 1) {
-                    const uint64_t q = c & (~c + 1);
-                    const int k = pass_gates(tm, qm, done, first, Sl | q, nullptr);
-                    if (k > best) {
-                        best = k;
-                        bq = q;
-                    }
-                }
-                if (!bq) break;
-                Sl |= bq;
-                cl = best;
+            std::vector<uint64_t> cands = {S};
+            for (int r = 0; r < kLookRanks; ++r) {
+                int c;
+                const uint64_t Sr = lookahead_tile_set(tm, qm, done, first, low, kmax, r, &c);
+                if (std::find(cands.begin(), cands.end(), Sr) == cands.end()) cands.push_back(Sr);
             }
-            if (cl >= cg) S = Sl;
+            int best = -1;
+            std::vector<char> d2;
+            for (uint64_t Sc : cands) {
+                Pass p;
+                const int c1 = pass_gates(tm, qm, done, first, Sc, &p);
+                d2 = done;
+                for (int gi : p.gates) d2[(size_t)gi] = 1;
+                const size_t f2 = next_first(d2, first);
+                int c2 = 0;
+                if (f2 < tm.size()) {
+                    int cl;
+                    lookahead_tile_set(tm, qm, d2, f2, low, kmax, 0, &cl);
+                    const int cg = pass_gates(tm, qm, d2, f2, greedy_tile_set(tm, qm, d2, f2, low, kmax), nullptr);
+                    c2 = std::max(cl, cg);
+                }
+                if (c1 + c2 > best) {
+                    best = c1 + c2;
+                    S = Sc;
+                }
+            }
         }
         Pass p;
         p.S = S;
         pass_gates(tm, qm, done, first, S, &p);
         for (int gi : p.gates) done[(size_t)gi] = 1;
         passes.push_back(std::move(p));
-        while (first < tm.size() && done[first]) ++first;
+        first = next_first(done, first);
     }
     return passes;
 }
