@@ -181,8 +181,11 @@ int sv_expectation_noalloc(const void *dev_amps, int n_qubits, int dtype, int n_
 /* Run a gate list on the state.  params (n_params doubles, may be NULL when
  * no op has param_index >= 0) supplies the angles of parametrised ops.
  * mode SV_RUN_PER_GATE launches one kernel per gate; SV_RUN_TILED lets the
- * scheduler apply consecutive gates that act inside one tile of qubits in a
- * single pass through on-chip memory, and stream the others. */
+ * scheduler group gates whose targets lie in one tile of qubits into single
+ * passes through on-chip memory (a gate may move ahead of gates on other
+ * qubits; each tile's qubits are chosen so that the pass and the next take
+ * many gates), and stream the others.  The result is that of applying the
+ * ops in order. */
 enum sv_run_mode { SV_RUN_PER_GATE = 0, SV_RUN_TILED = 1 };
 int sv_run(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
            int mode);
