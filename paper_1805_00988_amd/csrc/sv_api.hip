@@ -1006,16 +1006,18 @@ static uint64_t lookahead_tile_set(const std::vector<uint64_t> &tm, const std::v
 }
 
 // Commutation-aware pass scheduler.  Every pass holds the low lmin qubits
-// and up to mmax - lmin others.  Greedy: the others are taken in the order
-// the gates first need them.  With lookahead, the pass's tile set is chosen
-// among the greedy set and kLookRanks lookahead sets (the best first
-// addition and the next best ones), by the gates this pass and the next one
-// would take together (the next pass chosen by the better of the greedy
-// and the plain lookahead set).  On the random circuits of the benchmark:
-// 48 -> 33 passes at 32 qubits, 36 -> 28 at 30 qubits.
+// and up to mmax - lmin others.  Level 0 (greedy): the others are taken in
+// the order the gates first need them.  Level 1: the pass takes the greedy
+// set or the lookahead set, whichever takes more gates.  Level 2: the pass's
+// tile set is chosen among the greedy set and kLookRanks lookahead sets (the
+// best first addition and the next best ones) by the gates this pass and the
+// next one would take together (the next pass chosen as at level 1).  On the
+// random circuits of the benchmark: 48 -> 39 -> 33 passes at 32 qubits,
+// 36 -> 31 -> 28 at 30 qubits; level 2 costs about ten times the host time
+// of level 1 (about 20 ms for the 32-qubit circuit).
 constexpr int kLookRanks = 9;
 static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
-                                        int mmax, int lmin, bool lookahead = false) {
+                                        int mmax, int lmin, int lookahead = 0) {
     std::vector<Pass> passes;
     std::vector<char> done(tm.size(), 0);
     size_t first = 0;
@@ -1027,7 +1029,11 @@ static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const s
     };
     while (first < tm.size()) {
         uint64_t S = greedy_tile_set(tm, qm, done, first, low, kmax);
-        if (lookahead) {
+        if (lookahead == 1) {
+            int cl;
+            const uint64_t Sl = lookahead_tile_set(tm, qm, done, first, low, kmax, 0, &cl);
+            if (cl >= pass_gates(tm, qm, done, first, S, nullptr)) S = Sl;
+        } else if (lookahead >= 2) {
             std::vector<uint64_t> cands = {S};
             for (int r = 0; r < kLookRanks; ++r) {
                 int c;
@@ -1079,7 +1085,7 @@ static uint64_t tile_need(const Gate &g) {
 // the tile (sv_run's passes; the batch and adjoint passes keep every target
 // in the tile).
 static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, int lmin,
-                                  bool outside_diag = false, bool lookahead = false) {
+                                  bool outside_diag = false, int lookahead = 0) {
     (void)n;
     std::vector<uint64_t> tm(gs.size()), qm(gs.size());
     for (size_t i = 0; i < gs.size(); ++i) {
@@ -1087,6 +1093,14 @@ static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, 
         qm[i] = gs[i].qmask();
     }
     return schedule_masks(tm, qm, mmax, lmin, lookahead);
+}
+
+// Scheduler level for a state: the passes of larger states cost more GPU
+// time, so they get the more thorough (and slower) lookahead; small states
+// keep the greedy schedule, whose host time is a few microseconds per pass.
+static int lookahead_level(const sv_state *h) {
+    const double b = state_bytes(h);
+    return b >= 4.0 * (1ull << 30) ? 2 : (b >= 256.0 * (1ull << 20) ? 1 : 0);
 }
 
 // A phase gate of a pass with its target outside the tile and a control
@@ -1123,7 +1137,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
     // runs of 128 complex64 / 64 complex128 amplitudes: shorter runs cut
     // the number of passes but cost more per pass (measured)
     const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
-    std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin, true, true);
+    std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin, true, lookahead_level(h));
     // compile every tiled pass, stage all of them, upload once, launch in order
     std::vector<PassCode> code(passes.size());
     std::vector<size_t> offs(passes.size(), 0);
@@ -1599,7 +1613,7 @@ static std::vector<FusedPass> compile_fused(const sv_state *h, const std::vector
         for (int j = 0; j < bs[b].k; ++j) tm[b] |= 1ull << bs[b].q[j];
     }
     std::vector<FusedPass> out;
-    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h), true)) {
+    for (const Pass &p : schedule_masks(tm, tm, mmax, fused_lmin(h), lookahead_level(h))) {
         uint64_t needed = 0;
         for (int bi : p.gates) needed |= tm[bi];
         TileSpec sp{};
@@ -1673,7 +1687,7 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
     }
     std::vector<FusedPass> out;
     *n_blocks = 0;
-    for (const Pass &p : schedule_masks(tm, qm, mmax, fused_lmin(h), true)) {
+    for (const Pass &p : schedule_masks(tm, qm, mmax, fused_lmin(h), lookahead_level(h))) {
         uint64_t needed = 0;
         std::vector<Gate> sub;
         sub.reserve(p.gates.size());
