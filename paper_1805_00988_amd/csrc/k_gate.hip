@@ -439,7 +439,7 @@ __device__ __forceinline__ uint64_t tile_global(const TileSpec &sp, uint64_t bas
 // tile crosses LDS only between sweeps (a pass of one sweep never touches
 // it); each sweep ends with a barrier, which also keeps the next tile's
 // first LDS writes behind this tile's last LDS reads.
-template <typename T, int W, bool TWOQ>
+template <typename T, int W, bool TWOQ, bool LPH>
 __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const TileSpec &sp, uint64_t base,
                                  int m, const TileSweep *__restrict__ sweeps, int n_sweeps,
                                  const char *__restrict__ recs, uint32_t direct) {
@@ -491,7 +491,7 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
             }
             PhaseAcc<T, W> acc;
             acc.init();
-            run_records<T, W, TWOQ>(v, acc, gb, recs + S.rec_off, ng, base);
+            run_records<T, W, TWOQ, LPH>(v, acc, gb, recs + S.rec_off, ng, base);
             if (last) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) row[goff_of(j)] = v[j];
@@ -508,7 +508,7 @@ __device__ void tile_pass_direct(cpx<T> *__restrict__ state, cpx<T> *lds, const 
     }
 }
 
-template <typename T, int W, bool TWOQ>
+template <typename T, int W, bool TWOQ, bool LPH>
 __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v, TileSpec sp, int m,
                                                        const TileSweep *__restrict__ sweeps, int n_sweeps,
                                                        const char *__restrict__ recs,
@@ -522,21 +522,21 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(typename Vec<T>::type *v,
     for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
         uint64_t base = (uint64_t)tile << sp.L;
         for (int i = 0; i < sp.K; ++i) base = insert_zero(base, sp.high[i]);
-        tile_pass_direct<T, W, TWOQ>(state, lds, sp, base, m, sweeps, n_sweeps, recs, direct);
+        tile_pass_direct<T, W, TWOQ, LPH>(state, lds, sp, base, m, sweeps, n_sweeps, recs, direct);
     }
 }
 
-template <typename T, int W, bool TWOQ>
+template <typename T, int W, bool TWOQ, bool LPH = std::is_same<T, double>::value>
 static void launch_tile_t(typename Vec<T>::type *v, const TileSpec &spec, int m, const TileSweep *sw,
                           int n_sweeps, const char *g, uint64_t n_tiles, uint32_t direct, size_t lds,
                           hipStream_t s) {
-    (void)hipFuncSetAttribute((const void *)k_tile<T, W, TWOQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<T, W, TWOQ, LPH>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     // one workgroup per tile (measured faster than a capped grid looping
     // over tiles), and one thread per register group
     const unsigned grid = (unsigned)std::min<uint64_t>(n_tiles, 1u << 30);
     const unsigned threads = (unsigned)std::max(64, std::min(kTileThreads, (1 << m) >> W));
-    k_tile<T, W, TWOQ><<<grid, threads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles, direct);
+    k_tile<T, W, TWOQ, LPH><<<grid, threads, lds, s>>>(v, spec, m, sw, n_sweeps, g, n_tiles, direct);
 }
 
 template <int W>
@@ -548,7 +548,7 @@ static bool tile_staging_ok(int m, uint32_t direct) {
 }
 
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const char *dev_gates, bool two_qubit, uint32_t direct,
+                       int n_sweeps, const char *dev_gates, bool two_qubit, bool lane_phases, uint32_t direct,
                        hipStream_t s) {
     const int m = spec.L + spec.K;
     const int vbits = dtype == SV_C64 ? 1 : 0;
@@ -557,6 +557,18 @@ hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const
     const uint64_t n_tiles = 1ull << (n - m);
     const size_t lds = (size_t)(1u << m) * (dtype == SV_C64 ? 8 : 16);
     const int W = std::min(m, sweep_width(dtype));
+    // complex64 lane-bit phase lists: only the full-width instances hold
+    // them (the complex128 instances always do)
+    if (lane_phases && dtype == SV_C64) {
+        if (W != sweep_width(SV_C64) || !tile_staging_ok<4>(m, direct)) return hipErrorInvalidValue;
+        if (two_qubit)
+            launch_tile_t<float, 4, true, true>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates, n_tiles,
+                                                direct, lds, s);
+        else
+            launch_tile_t<float, 4, false, true>((float4 *)amps, spec, m, dev_sweeps, n_sweeps, dev_gates,
+                                                 n_tiles, direct, lds, s);
+        return hipGetLastError();
+    }
 #define SV_TILE_CASE(WW, Q)                                                                        \
     if (W == WW && two_qubit == Q) {                                                               \
         if (!tile_staging_ok<WW>(m, direct)) return hipErrorInvalidValue;                          \

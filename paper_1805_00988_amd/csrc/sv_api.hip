@@ -306,6 +306,7 @@ struct PassCode {
     int m = 0;
     double flops_per_amp = 0.0; // algorithmic flops of the pass per state amplitude
     bool two_qubit = false;     // holds SK_2Q records
+    bool lane_phases = false;   // holds SK_LPH records
     uint32_t direct = 0;        // kDirectFirst / kDirectLast (launch_tile)
     std::vector<TileSweep> sweeps;
     std::vector<TileGate> gates; // records in sweep order (host form)
@@ -600,7 +601,7 @@ static TileGate encode_probe(const TileSpec &sp, const std::vector<int> &qset, c
 constexpr int kMinPhaseRun = 4;
 
 static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *> &gs, int sweep_w, bool f32,
-                             const std::vector<const Probe *> *probes = nullptr) {
+                             const std::vector<const Probe *> *probes = nullptr, bool lph_f32 = false) {
     PassCode pc;
     pc.sp = sp;
     pc.m = sp.L + sp.K;
@@ -662,12 +663,15 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
             if (!pending) return;
             // groups conditioned on one lane bit and nothing outside the
             // tile: one SK_LPH record per slot lists (bit, phase) for all of
-            // them, so the lanes walk one record instead of one per bit
-            // (complex128 only: in the complex64 kernel the extra record kind
-            // slowed the other passes more than it saved)
+            // them, so the lanes walk one record instead of one per bit.
+            // Complex64 passes carry them only when launched on the kernel
+            // instances compiled with them (lph_f32, full sweep width): in
+            // the common instance the extra record kind slowed the other
+            // passes more than it saved
             std::vector<std::vector<std::pair<uint32_t, std::complex<double>>>> lph(W + 1);
             std::vector<char> in_lph(groups.size(), 0);
-            for (size_t gi = 0; gi < groups.size() && !f32; ++gi) {
+            const bool use_lph = !f32 || (lph_f32 && W == kSweepW);
+            for (size_t gi = 0; gi < groups.size() && use_lph; ++gi) {
                 const auto &grp = groups[gi];
                 const uint32_t lm = grp.first.second;
                 if (__builtin_popcount(lm) != 1) continue;
@@ -689,6 +693,7 @@ static PassCode compile_pass(const TileSpec &sp, const std::vector<const Gate *>
                     continue;
                 }
                 for (size_t e0 = 0; e0 < ents.size(); e0 += (size_t)max_entries) {
+                    pc.lane_phases = true;
                     TileGate r{};
                     r.kind = SK_LPH;
                     r.b0 = slot_i;
@@ -899,8 +904,8 @@ static int launch_pass(sv_state *h, const PassCode &pc, size_t off) {
     const TileSweep *sw = reinterpret_cast<const TileSweep *>(h->d_arena + off);
     const char *gt = h->d_arena + off + align256(pc.sweeps.size() * sizeof(TileSweep));
     Timed tm(h, K_TILE, 2.0 * state_bytes(h), pc.flops_per_amp * (double)(1ull << h->n));
-    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, pc.two_qubit, pc.direct,
-                       h->stream));
+    SV_HIP(launch_tile(h->amps, h->n, h->dtype, pc.sp, sw, (int)pc.sweeps.size(), gt, pc.two_qubit, pc.lane_phases,
+                       pc.direct, h->stream));
     return SV_OK;
 }
 
@@ -1156,7 +1161,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         for (int gi : p.gates) local.push_back(retarget_phase(gs[gi], tile_qubits(sp)));
         std::vector<const Gate *> ptrs;
         for (const Gate &g : local) ptrs.push_back(&g);
-        code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64);
+        code[pi] = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64, nullptr, true);
         offs[pi] = total;
         total += align256(code[pi].bytes());
     }
@@ -1735,7 +1740,7 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
             fp.plain = true;
             fp.sp = sp;
             fp.m = mtile;
-            fp.code = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64);
+            fp.code = compile_pass(sp, ptrs, sweep_width(h->dtype), h->dtype == SV_C64, nullptr, true);
             fp.cost = plain_pass_cost(h, fp.code);
             if (fp.cost < best.cost) {
                 best = std::move(fp);

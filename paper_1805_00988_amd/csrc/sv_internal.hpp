@@ -218,7 +218,7 @@ hipError_t launch_scale(void *amps, int n, int dtype, uint64_t set_mask, const d
 // wave's accesses stay contiguous).
 constexpr uint32_t kDirectFirst = 1, kDirectLast = 2;
 hipError_t launch_tile(void *amps, int n, int dtype, const TileSpec &spec, const TileSweep *dev_sweeps,
-                       int n_sweeps, const char *dev_recs, bool two_qubit, uint32_t direct,
+                       int n_sweeps, const char *dev_recs, bool two_qubit, bool lane_phases, uint32_t direct,
                        hipStream_t s);
 int tile_max_qubits(int dtype);
 int tile_launch_qubits(int dtype);

@@ -480,8 +480,10 @@ __device__ __forceinline__ void phase_flush(cpx<T> (&v)[1 << W], PhaseAcc<T, W> 
 // are rewritten, keep the compiler from holding the group in place across
 // the dispatch, so passes without them use kernels without that path.
 // PHASES = false compiles the gathered-phase kinds out, for streams that
-// carry none (the adjoint's reverse passes).
-template <typename T, int W, bool TWOQ, bool PHASES = true>
+// carry none (the adjoint's reverse passes); LPH compiles in the lane-bit
+// phase lists (always for complex128; complex64 streams carry them only for
+// the kernel instances launched with them).
+template <typename T, int W, bool TWOQ, bool PHASES = true, bool LPH = std::is_same<T, double>::value>
 __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
                                              const GateHot &h, const TileGate &G, uint64_t base) {
     const int kind = h.kind;
@@ -516,7 +518,7 @@ __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
 #pragma unroll
         for (int w = 1; w < kPtabWindows; ++w) u = cmul(u, f[w]);
         phase_gather<T, W>(acc, h.b0, ok ? u : cpx<T>{T(1), T(0)});
-    } else if (PHASES && std::is_same<T, double>::value && kind == SK_LPH) {
+    } else if (PHASES && LPH && kind == SK_LPH) {
         // per-lane factor: the phases of the lane bits its group holds
         const char *e = reinterpret_cast<const char *>(&G) + kRecordHead;
         cpx<T> u{T(1), T(0)};
@@ -571,17 +573,17 @@ __device__ __forceinline__ void sweep_gate_h(cpx<T> (&v)[1 << W], PhaseAcc<T, W>
     }
 }
 
-template <typename T, int W, bool TWOQ>
+template <typename T, int W, bool TWOQ, bool LPH = std::is_same<T, double>::value>
 __device__ __forceinline__ void sweep_gate_t(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
                                              const TileGate &G, uint64_t base) {
     const GateHot h = *reinterpret_cast<const GateHot *>(&G);
-    sweep_gate_h<T, W, TWOQ>(v, acc, gb, h, G, base);
+    sweep_gate_h<T, W, TWOQ, true, LPH>(v, acc, gb, h, G, base);
 }
 
 // Apply the ng packed records starting at rp to one register group.  (A
 // variant that loads record i+1's head while record i is applied needs a
 // second set of scalar registers for it and spills.)
-template <typename T, int W, bool TWOQ>
+template <typename T, int W, bool TWOQ, bool LPH = std::is_same<T, double>::value>
 __device__ __forceinline__ void run_records(cpx<T> (&v)[1 << W], PhaseAcc<T, W> &acc, uint32_t gb,
                                             const char *__restrict__ rp, int ng, uint64_t base) {
     for (int gi = 0; gi < ng; ++gi) {
@@ -589,7 +591,7 @@ __device__ __forceinline__ void run_records(cpx<T> (&v)[1 << W], PhaseAcc<T, W> 
         // advance before the gate: its inline assembly would make the
         // compiler read the size again after it
         rp += G.size;
-        sweep_gate_t<T, W, TWOQ>(v, acc, gb, G, base);
+        sweep_gate_t<T, W, TWOQ, LPH>(v, acc, gb, G, base);
     }
 }
 
