@@ -10,7 +10,9 @@ benchmark times, on outputs computable independently of the full state:
   one, for the tile-pass path and for the fused path.
 The one-launch-per-gate path of Alg. 1 (streamed kernels, through
 sv_apply_gate and through sv_run in per-gate mode) is checked at these sizes
-too, where amplitude indices pass 2^31.
+too, where amplitude indices pass 2^31.  At 28 qubits complex128 (4 GiB, the
+size from which the scheduler uses its two-pass lookahead) the headline
+recipe is compared with the FP64 oracle on every amplitude.
 
 Tolerances: complex128 within 1e-12 per amplitude.  complex64: the 2-norm
 bound tau = 4 sqrt(2) eps32 G of G gates (helpers.c64_bound) taken
@@ -180,5 +182,30 @@ def test_block_product_full_size_per_gate(dtype, n):
     st = sv.State(n, dtype).run(circ.gates, mode=sv.SV_RUN_PER_GATE)
     idx = sample_indices(n, 4096, 37)
     check(gpu_amplitudes(st, idx), block_reference(circ, blocks, idx), dtype, len(circ))
+    del st
+    torch.cuda.empty_cache()
+
+
+def test_headline_recipe_28q_complex128_whole_state_vs_oracle():
+    """The headline workload's two circuits (QFT of a seeded random basis
+    state, then the depth-20 random circuit with n/2 CNOTs per layer) at 28
+    qubits complex128 (4 GiB: the size from which the scheduler's two-pass
+    lookahead builds the passes), tiled, against the FP64 oracle on every
+    amplitude (the oracle takes tens of seconds on the host)."""
+    n = 28
+    q, r = C.config1(n, 3)
+    ref = O.basis_state(n, q.basis)
+    O.run_gates(n, q.gates, ref)
+    O.run_gates(n, r.gates, ref)
+    st = sv.State(n, "c128")
+    st.set_basis(q.basis)
+    st.run(q.gates, mode=sv.SV_RUN_TILED)
+    st.run(r.gates, mode=sv.SV_RUN_TILED)
+    worst = 0.0
+    step = 1 << 24
+    for c0 in range(0, 1 << n, step):
+        got = st.amps[c0:c0 + step].cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - ref[c0:c0 + step]))))
+    assert worst <= C128_ATOL, worst
     del st
     torch.cuda.empty_cache()
