@@ -38,10 +38,30 @@ struct AV<double> {
     __device__ static void put(double2 &v, int, cpx<double> c) { v.x = c.re; v.y = c.im; }
 };
 
+// x of another lane of the same 16-lane row, moved by DPP (both halves of
+// the double; no LDS round trip)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_f64(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, in a fixed order: within each row of 16 lanes by
+// rotations of 8 and 4 and quad swaps of 2 and 1 (every lane then holds its
+// row's sum), then the four rows' sums; every lane returns the total.
 __device__ __forceinline__ double wave_sum_d(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp_f64<0x128>(x); // row_ror:8
+    x += dpp_f64<0x124>(x); // row_ror:4
+    x += dpp_f64<0x4E>(x);  // quad_perm [2,3,0,1]
+    x += dpp_f64<0xB1>(x);  // quad_perm [1,0,3,2]
+    return (lane_f64(x, 0) + lane_f64(x, 16)) + (lane_f64(x, 32) + lane_f64(x, 48));
 }
 
 __device__ __forceinline__ double block_sum_d(double x) {
