@@ -190,6 +190,21 @@ enum sv_run_mode { SV_RUN_PER_GATE = 0, SV_RUN_TILED = 1 };
 int sv_run(sv_handle h, const sv_op *ops, int n_ops, const double *params, int n_params,
            int mode);
 
+/* The passes sv_run's tiled mode forms for a register of n_qubits of the
+ * given dtype (host only: no state, no device call).  Gates apply in the
+ * order of Sec. 2.3 (the ops in sequence); a pass may take a gate ahead of
+ * gates left behind only when they share no qubit.  level 0 is the greedy
+ * scheduler, 1 the lookahead, 2 the two-pass lookahead, -1 the level sv_run
+ * uses for that state size.  gate_pass (n_ops ints, caller-owned) receives
+ * the pass index of every op; pass_qubits (max_passes values) the qubit mask
+ * of each pass's tile (bit q = qubit q), or 0 for a single gate sv_run
+ * streams instead; *n_passes the pass count.  SV_EINVAL for n_qubits outside
+ * [1, 40], an unknown dtype, level outside [-1, 2], NULL outputs, an invalid
+ * op, or more passes than max_passes (then *n_passes still holds the
+ * count). */
+int sv_schedule(int n_qubits, int dtype, const sv_op *ops, int n_ops, const double *params, int n_params,
+                int level, int max_passes, int *gate_pass, uint64_t *pass_qubits, int *n_passes);
+
 /* Greedy fusion (host, FP64): walk ops in order, growing a block whose qubit
  * set (targets and controls) has at most k_max qubits; multiply each gate
  * into the block's 2^k x 2^k matrix; start a new block when a gate does not

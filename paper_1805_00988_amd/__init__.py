@@ -19,7 +19,7 @@ from ._lib import (GATE_KINDS, SV_C64, SV_C128, SV_PREC_FP32, SV_PREC_NATIVE,
                    SV_PREC_SPLIT_BF16, SV_RUN_PER_GATE, SV_RUN_TILED, SVError, sv_op)
 
 __all__ = ["State", "sv_alloc", "sv_free", "sv_set_basis", "sv_apply_gate", "sv_apply_fused",
-           "sv_probabilities", "sv_expectation", "sv_expectation_noalloc", "sv_run", "sv_fuse", "sv_run_fused", "sv_fused_tune",
+           "sv_probabilities", "sv_expectation", "sv_expectation_noalloc", "sv_run", "sv_schedule", "sv_fuse", "sv_run_fused", "sv_fused_tune",
            "sv_adjoint_grad", "sv_state_bytes", "ops_from_gates", "SV_C64", "SV_C128",
            "SV_PREC_NATIVE", "SV_PREC_FP32", "SV_PREC_SPLIT_BF16", "SV_RUN_PER_GATE",
            "SV_RUN_TILED", "SVError", "Batch"]
@@ -208,6 +208,21 @@ def sv_run(h, gates, params=None, mode: int = SV_RUN_TILED) -> None:
     ops = ops_from_gates(gates)
     pp, n_p, keep = _params(params)
     _lib.check(_lib.load().sv_run(h, _opptr(ops), len(gates), pp, n_p, int(mode)))
+
+
+def sv_schedule(n_qubits: int, dtype, gates, level: int = -1, params=None):
+    """The passes of sv_run's tiled mode (host library, no GPU): (pass index
+    of every gate as an int array, list of each pass's tile-qubit mask, 0 for
+    a gate sv_run streams)."""
+    ops = ops_from_gates(gates)
+    pp, n_p, keep = _params(params)
+    cap = max(1, len(gates))
+    gp = np.full(max(1, len(gates)), -1, np.int32)
+    pq = np.zeros(cap, np.uint64)
+    npass = ctypes.c_int()
+    _lib.check(_lib.load().sv_schedule(n_qubits, _dtype_code(dtype), _opptr(ops), len(gates), pp, n_p, int(level),
+                                       cap, _iptr(gp), _u64ptr(pq), ctypes.byref(npass)))
+    return gp[:len(gates)].copy(), [int(x) for x in pq[:npass.value]]
 
 
 def sv_fuse(n_qubits: int, gates, k_max: int, params=None, max_blocks: Optional[int] = None):

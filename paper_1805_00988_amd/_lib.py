@@ -23,7 +23,7 @@ GATE_KINDS = {"H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6,
 EXPORTED = ("sv_state_bytes", "sv_alloc", "sv_free", "sv_set_basis", "sv_set_stream", "sv_sync",
             "sv_data", "sv_apply_gate", "sv_apply_fused", "sv_probabilities", "sv_expectation",
             "sv_expectation_noalloc", "sv_marginals", "sv_collapse", "sv_measure", "sv_sample",
-            "sv_run", "sv_fuse", "sv_run_fused", "sv_fused_tune", "sv_adjoint_grad", "sv_batch_create",
+            "sv_run", "sv_schedule", "sv_fuse", "sv_run_fused", "sv_fused_tune", "sv_adjoint_grad", "sv_batch_create",
             "sv_batch_run", "sv_batch_results", "sv_batch_output", "sv_batch_state",
             "sv_batch_tune", "sv_batch_config", "sv_batch_free", "sv_timing", "sv_timing_read", "sv_last_error",
             "sv_version")
@@ -77,6 +77,7 @@ _PROTOS = {
     "sv_measure": (_I, [_P, _U64, ctypes.c_double, _U64P, _DP]),
     "sv_sample": (_I, [_P, _I, _DP, _U64P]),
     "sv_run": (_I, [_P, _OPP, _I, _DP, _I, _I]),
+    "sv_schedule": (_I, [_I, _I, _OPP, _I, _DP, _I, _I, _I, _IP, _U64P, _IP]),
     "sv_fuse": (_I, [_I, _OPP, _I, _DP, _I, _I, _I, _IP, _IP, _DP, _IP, _IP]),
     "sv_fused_tune": (_I, [_P, _OPP, _I, _DP, _I, _I, _I, _I, _IP, _IP, _DP]),
     "sv_run_fused": (_I, [_P, _OPP, _I, _DP, _I, _I, _I, _IP]),

@@ -1103,10 +1103,11 @@ static std::vector<Pass> schedule(const std::vector<Gate> &gs, int n, int mmax, 
 // Scheduler level for a state: the passes of larger states cost more GPU
 // time, so they get the more thorough (and slower) lookahead; small states
 // keep the greedy schedule, whose host time is a few microseconds per pass.
-static int lookahead_level(const sv_state *h) {
-    const double b = state_bytes(h);
+static int lookahead_level_for(int n, int dtype) {
+    const double b = std::ldexp(dtype == SV_C64 ? 8.0 : 16.0, n);
     return b >= 4.0 * (1ull << 30) ? 2 : (b >= 256.0 * (1ull << 20) ? 1 : 0);
 }
+static int lookahead_level(const sv_state *h) { return lookahead_level_for(h->n, h->dtype); }
 
 // A phase gate of a pass with its target outside the tile and a control
 // inside: the same gate with that control as the target (the gate is
@@ -1125,10 +1126,16 @@ static Gate retarget_phase(const Gate &g, uint64_t S) {
 
 // A single gate that the streamed kernels cannot take: a two-qubit gate with
 // a target inside a 16-byte complex64 vector.
-static bool needs_tile(const sv_state *h, const Gate &g) {
-    const int vb = vbits_of(h->dtype);
+static bool needs_tile(int dtype, const Gate &g) {
+    const int vb = vbits_of(dtype);
     return g.k == 2 && (g.t[0] < vb || g.t[1] < vb);
 }
+
+// Tile size and low block of sv_run's plain passes: runs of 128 complex64 /
+// 64 complex128 amplitudes (shorter runs cut the number of passes but cost
+// more per pass, measured).
+static int plain_tile_qubits(int n, int dtype) { return std::min(n, tile_max_qubits(dtype)); }
+static int plain_low_qubits(int n, int dtype) { return std::min(n, dtype == SV_C64 ? 7 : 6); }
 
 static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
     if (mode == SV_RUN_PER_GATE) {
@@ -1138,10 +1145,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
         }
         return SV_OK;
     }
-    const int mmax = std::min(h->n, tile_max_qubits(h->dtype));
-    // runs of 128 complex64 / 64 complex128 amplitudes: shorter runs cut
-    // the number of passes but cost more per pass (measured)
-    const int lmin = std::min(h->n, h->dtype == SV_C64 ? 7 : 6);
+    const int mmax = plain_tile_qubits(h->n, h->dtype), lmin = plain_low_qubits(h->n, h->dtype);
     std::vector<Pass> passes = schedule(gs, h->n, mmax, lmin, true, lookahead_level(h));
     // compile every tiled pass, stage all of them, upload once, launch in order
     std::vector<PassCode> code(passes.size());
@@ -1150,7 +1154,7 @@ static int run_gates(sv_state *h, const std::vector<Gate> &gs, int mode) {
     size_t total = 0;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const Pass &p = passes[pi];
-        tiled[pi] = p.gates.size() > 1 || (p.gates.size() == 1 && needs_tile(h, gs[p.gates[0]]));
+        tiled[pi] = p.gates.size() > 1 || (p.gates.size() == 1 && needs_tile(h->dtype, gs[p.gates[0]]));
         if (!tiled[pi]) continue;
         uint64_t needed = 0;
         for (int gi : p.gates) needed |= tile_need(gs[gi]);
@@ -1731,7 +1735,7 @@ static std::vector<FusedPass> compile_fused_gates(const sv_state *h, const std::
         local.reserve(sub.size());
         for (const Gate &g : sub) {
             local.push_back(retarget_phase(g, S));
-            plain_ok = plain_ok && (tile_need(local.back()) & ~S) == 0 && !needs_tile(h, g);
+            plain_ok = plain_ok && (tile_need(local.back()) & ~S) == 0 && !needs_tile(h->dtype, g);
         }
         if (plain_ok) {
             std::vector<const Gate *> ptrs;
@@ -2609,6 +2613,37 @@ int sv_fuse(int n_qubits, const sv_op *ops, int n_ops, const double *params, int
             m[2 * i] = B.M[i].real();
             m[2 * i + 1] = B.M[i].imag();
         }
+    }
+    return SV_OK;
+}
+
+int sv_schedule(int n_qubits, int dtype, const sv_op *ops, int n_ops, const double *params, int n_params,
+                int level, int max_passes, int *gate_pass, uint64_t *pass_qubits, int *n_passes) {
+    if (n_qubits < 1 || n_qubits > 40) return fail(SV_EINVAL, "n_qubits must be in [1, 40]");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    if (level < -1 || level > 2) return fail(SV_EINVAL, "level must be in [-1, 2]");
+    if (!n_passes || max_passes < 0 || (n_ops > 0 && !gate_pass) || (max_passes > 0 && !pass_qubits))
+        return fail(SV_EINVAL, "NULL output");
+    std::vector<Gate> gs;
+    int rc = parse_ops(nullptr, n_qubits, ops, n_ops, params, n_params, gs);
+    if (rc) return rc;
+    const int mmax = plain_tile_qubits(n_qubits, dtype), lmin = plain_low_qubits(n_qubits, dtype);
+    const int lv = level < 0 ? lookahead_level_for(n_qubits, dtype) : level;
+    const std::vector<Pass> passes = schedule(gs, n_qubits, mmax, lmin, true, lv);
+    *n_passes = (int)passes.size();
+    if ((int)passes.size() > max_passes) return fail(SV_EINVAL, "more passes than max_passes");
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const Pass &p = passes[pi];
+        uint64_t needed = 0;
+        for (int gi : p.gates) {
+            gate_pass[gi] = (int)pi;
+            needed |= tile_need(gs[(size_t)gi]);
+        }
+        // the tile run_gates builds for the pass, or 0 for a single gate it streams
+        const bool tiled = p.gates.size() > 1 || (p.gates.size() == 1 && needs_tile(dtype, gs[(size_t)p.gates[0]]));
+        TileSpec sp{};
+        if (tiled) tile_layout(n_qubits, mmax, lmin, needed, &sp);
+        pass_qubits[pi] = tiled ? tile_qubits(sp) : 0;
     }
     return SV_OK;
 }
