@@ -929,7 +929,7 @@ static int tile_single(sv_state *h, const Gate &g) {
 // of the scan, so every pair of gates sharing a qubit keeps its order.
 // Gates a pass with tile qubits S would take, in order: a gate joins if it
 // shares no qubit with a gate left behind and S holds the qubits it needs.
-static int pass_gates(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
+static int pass_gates(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm, uint64_t all,
                       const std::vector<char> &done, size_t first, uint64_t S, Pass *take) {
     uint64_t blocked = 0;
     int cnt = 0;
@@ -937,6 +937,7 @@ static int pass_gates(const std::vector<uint64_t> &tm, const std::vector<uint64_
         if (done[i]) continue;
         if ((qm[i] & blocked) || (tm[i] & ~S)) {
             blocked |= qm[i];
+            if (blocked == all) break; // every later gate shares a qubit with one left behind
             continue;
         }
         ++cnt;
@@ -947,11 +948,11 @@ static int pass_gates(const std::vector<uint64_t> &tm, const std::vector<uint64_
 
 // Greedy tile set: the qubits beyond the low block are taken in the order
 // the gates first need them, while they fit.
-static uint64_t greedy_tile_set(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
+static uint64_t greedy_tile_set(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm, uint64_t all,
                                 const std::vector<char> &done, size_t first, uint64_t low, int kmax) {
     uint64_t S = low, blocked = 0;
     int used = 0;
-    for (size_t i = first; i < tm.size(); ++i) {
+    for (size_t i = first; i < tm.size() && blocked != all; ++i) {
         if (done[i]) continue;
         if (qm[i] & blocked) {
             blocked |= qm[i];
@@ -974,15 +975,15 @@ static uint64_t greedy_tile_set(const std::vector<uint64_t> &tm, const std::vect
 // 12 candidates), each time the one that lets the pass take the most gates;
 // the first addition takes the candidate of rank 'rank' instead of the best.
 // *count receives the gates the pass takes.
-static uint64_t lookahead_tile_set(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
+static uint64_t lookahead_tile_set(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm, uint64_t all,
                                    const std::vector<char> &done, size_t first, uint64_t low, int kmax, int rank,
                                    int *count) {
     uint64_t S = low;
-    int c = pass_gates(tm, qm, done, first, S, nullptr);
+    int c = pass_gates(tm, qm, all, done, first, S, nullptr);
     std::vector<std::pair<int, uint64_t>> sc;
     for (int used = 0; used < kmax; ++used) {
         uint64_t cand = 0, blocked = 0;
-        for (size_t i = first; i < tm.size() && __builtin_popcountll(cand) < 12; ++i) {
+        for (size_t i = first; i < tm.size() && __builtin_popcountll(cand) < 12 && blocked != all; ++i) {
             if (done[i]) continue;
             if (qm[i] & blocked) {
                 blocked |= qm[i];
@@ -996,7 +997,7 @@ static uint64_t lookahead_tile_set(const std::vector<uint64_t> &tm, const std::v
         sc.clear();
         for (uint64_t cc = cand; cc; cc &= cc - 1) {
             const uint64_t q = cc & (~cc + 1);
-            sc.push_back({pass_gates(tm, qm, done, first, S | q, nullptr), q});
+            sc.push_back({pass_gates(tm, qm, all, done, first, S | q, nullptr), q});
         }
         std::sort(sc.begin(), sc.end(), [](const std::pair<int, uint64_t> &x, const std::pair<int, uint64_t> &y) {
             return x.first > y.first || (x.first == y.first && x.second < y.second);
@@ -1018,8 +1019,9 @@ static uint64_t lookahead_tile_set(const std::vector<uint64_t> &tm, const std::v
 // best first addition and the next best ones) by the gates this pass and the
 // next one would take together (the next pass chosen as at level 1).  On the
 // random circuits of the benchmark: 48 -> 39 -> 33 passes at 32 qubits,
-// 36 -> 31 -> 28 at 30 qubits; level 2 costs about ten times the host time
-// of level 1 (about 20 ms for the 32-qubit circuit).
+// 36 -> 31 -> 28 at 30 qubits; level 2 costs about six times the host time
+// of level 1 (about 11 ms for the 32-qubit circuit).  The scans stop once
+// every qubit is blocked by a gate left behind.
 constexpr int kLookRanks = 9;
 static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const std::vector<uint64_t> &qm,
                                         int mmax, int lmin, int lookahead = 0) {
@@ -1028,36 +1030,38 @@ static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const s
     size_t first = 0;
     const uint64_t low = lmin >= 64 ? ~0ull : ((1ull << lmin) - 1ull);
     const int kmax = std::max(0, mmax - lmin);
+    uint64_t all = 0; // every qubit some gate touches
+    for (uint64_t m : qm) all |= m;
     auto next_first = [&](const std::vector<char> &d, size_t f) {
         while (f < tm.size() && d[f]) ++f;
         return f;
     };
     while (first < tm.size()) {
-        uint64_t S = greedy_tile_set(tm, qm, done, first, low, kmax);
+        uint64_t S = greedy_tile_set(tm, qm, all, done, first, low, kmax);
         if (lookahead == 1) {
             int cl;
-            const uint64_t Sl = lookahead_tile_set(tm, qm, done, first, low, kmax, 0, &cl);
-            if (cl >= pass_gates(tm, qm, done, first, S, nullptr)) S = Sl;
+            const uint64_t Sl = lookahead_tile_set(tm, qm, all, done, first, low, kmax, 0, &cl);
+            if (cl >= pass_gates(tm, qm, all, done, first, S, nullptr)) S = Sl;
         } else if (lookahead >= 2) {
             std::vector<uint64_t> cands = {S};
             for (int r = 0; r < kLookRanks; ++r) {
                 int c;
-                const uint64_t Sr = lookahead_tile_set(tm, qm, done, first, low, kmax, r, &c);
+                const uint64_t Sr = lookahead_tile_set(tm, qm, all, done, first, low, kmax, r, &c);
                 if (std::find(cands.begin(), cands.end(), Sr) == cands.end()) cands.push_back(Sr);
             }
             int best = -1;
             std::vector<char> d2;
             for (uint64_t Sc : cands) {
                 Pass p;
-                const int c1 = pass_gates(tm, qm, done, first, Sc, &p);
+                const int c1 = pass_gates(tm, qm, all, done, first, Sc, &p);
                 d2 = done;
                 for (int gi : p.gates) d2[(size_t)gi] = 1;
                 const size_t f2 = next_first(d2, first);
                 int c2 = 0;
                 if (f2 < tm.size()) {
                     int cl;
-                    lookahead_tile_set(tm, qm, d2, f2, low, kmax, 0, &cl);
-                    const int cg = pass_gates(tm, qm, d2, f2, greedy_tile_set(tm, qm, d2, f2, low, kmax), nullptr);
+                    lookahead_tile_set(tm, qm, all, d2, f2, low, kmax, 0, &cl);
+                    const int cg = pass_gates(tm, qm, all, d2, f2, greedy_tile_set(tm, qm, all, d2, f2, low, kmax), nullptr);
                     c2 = std::max(cl, cg);
                 }
                 if (c1 + c2 > best) {
@@ -1068,7 +1072,7 @@ static std::vector<Pass> schedule_masks(const std::vector<uint64_t> &tm, const s
         }
         Pass p;
         p.S = S;
-        pass_gates(tm, qm, done, first, S, &p);
+        pass_gates(tm, qm, all, done, first, S, &p);
         for (int gi : p.gates) done[(size_t)gi] = 1;
         passes.push_back(std::move(p));
         first = next_first(done, first);
