@@ -10,7 +10,10 @@ benchmark times, on outputs computable independently of the full state:
   one, for the tile-pass path and for the fused path.
 The one-launch-per-gate path of Alg. 1 (streamed kernels, through
 sv_apply_gate and through sv_run in per-gate mode) is checked at these sizes
-too, where amplitude indices pass 2^31.  At 28 qubits complex128 (4 GiB, the
+too, where amplitude indices pass 2^31, and the largest states the suite
+allocates (34 qubits complex64, 33 qubits complex128: 128 GiB, indices past
+2^32) run the QFT's tile passes and both streamed kernels.  At 28 qubits
+complex128 (4 GiB, the
 size from which the scheduler uses its two-pass lookahead) the headline
 recipe is compared with the FP64 oracle on every amplitude.
 
@@ -207,5 +210,43 @@ def test_headline_recipe_28q_complex128_whole_state_vs_oracle():
         got = st.amps[c0:c0 + step].cpu().numpy()
         worst = max(worst, float(np.max(np.abs(got - ref[c0:c0 + step]))))
     assert worst <= C128_ATOL, worst
+    del st
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 34), ("c128", 33)])
+def test_largest_states_qft_then_streamed_gates(dtype, n):
+    """The largest states this suite allocates (128 GiB, amplitude indices up
+    to 2^34): the QFT of a random basis state through tile passes, then H on
+    the top qubit (streamed pair kernel) and a controlled phase between the
+    top qubit and qubit 0 (subspace kernel), one launch each through
+    sv_apply_gate; sampled amplitudes, half of them at indices >= 2^32,
+    against the closed form, and the FP64 norm from sv_expectation with the
+    empty Z-string."""
+    x = C.random_basis(n, 9)
+    circ = C.qft_circuit(n, x)
+    rng = np.random.default_rng(41)
+    lo = rng.integers(0, 1 << 32, size=2048, dtype=np.int64)
+    hi = rng.integers(1 << 32, 1 << n, size=2048, dtype=np.int64)
+    top = n - 1
+    idx = np.unique(np.concatenate([lo, hi, [0, (1 << n) - 1, 1 << 32, (1 << 32) - 1]]).astype(np.int64))
+    st = sv.State(n, dtype).set_basis(x)
+    st.run(circ.gates, mode=sv.SV_RUN_TILED)
+    ref = qft_closed_form(n, x, idx)
+    check(gpu_amplitudes(st, idx), ref, dtype, len(circ))
+    assert abs(st.expectation([0], [1.0]) - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
+    # H on the top qubit: psi'_y0 = (psi_y0 + psi_y1)/sqrt2, psi'_y1 = (psi_y0 - psi_y1)/sqrt2
+    st.apply(O.gate_matrix("H"), (top,))
+    y0 = idx & ~np.int64(1 << top)
+    a0 = qft_closed_form(n, x, y0)
+    a1 = qft_closed_form(n, x, y0 | np.int64(1 << top))
+    bit = (idx >> top) & 1
+    ref = np.where(bit == 0, a0 + a1, a0 - a1) / math.sqrt(2.0)
+    theta = 0.731
+    st.apply(O.gate_matrix("U1", theta), (0,), (top,))
+    both = ((idx >> top) & 1) & (idx & 1)
+    ref = ref * np.where(both == 1, np.exp(1j * theta), 1.0)
+    check(gpu_amplitudes(st, idx), ref, dtype, len(circ) + 2)
+    assert abs(st.expectation([0], [1.0]) - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
     del st
     torch.cuda.empty_cache()
